@@ -1,0 +1,300 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each check here is independent of the oracle's own code path: hand-derived
+closed forms, a library eigensolver on the completed matrix, identities the
+paper proves (Theorems 1 and 2, the Lemma of Section 3.1, the power series of
+Section 2.2) evaluated with scipy.sparse matrices built here from the edge
+list, and brute force on tiny graphs.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads as wl
+
+D = 0.85
+ORDERS = ["per", "rand", "max", "sweep", "op", "op2"]
+
+
+def P_sparse(g):
+    """Column-stochastic P (zero dangling columns) built from the edge list."""
+    src, dst = g.edges()
+    deg = g.outdeg
+    return sp.csr_matrix((1.0 / deg[src], (dst, src)), shape=(g.n, g.n))
+
+
+def all_solvers(g, d, v=None, tol=1e-14):
+    """Normalised results of every oracle route."""
+    runs = {"power": oracle.power(g, d, tol, v, max_iter=100_000),
+            "sets_c1": oracle.diter_sets(g, d, tol, c=1.0, v=v, max_rounds=100_000),
+            "sets_jacobi": oracle.diter_sets(g, d, tol, c=0.0, v=v, max_rounds=100_000)}
+    for o in ORDERS:
+        runs[o] = oracle.diter(g, d, tol, order=o, v=v, seed=7, max_picks=2_000_000)
+    for name, r in runs.items():
+        assert r["converged"], name
+    out = {name: r["x"] for name, r in runs.items()}
+    out["dense"] = oracle.dense_exact(g, d, v)[1]
+    return out
+
+
+# ------------------------------------------------------------ closed forms
+
+def test_transition_matrix_by_hand():
+    # 0->1, 0->2, 0->2 (repeated), 1->1 (self-loop), 2 dangling
+    g = wl.from_edges(3, [0, 0, 0, 1], [1, 2, 2, 1])
+    P = oracle.transition_dense(g)
+    expect = np.array([[0, 0, 0], [1 / 3, 1, 0], [2 / 3, 0, 0]])
+    np.testing.assert_allclose(P, expect, atol=0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 50])
+def test_cycle_uniform(n):
+    g = wl.cycle(n) if n > 1 else wl.from_edges(1, [0], [0])
+    for name, x in all_solvers(g, D).items():
+        np.testing.assert_allclose(x, np.full(n, 1.0 / n), atol=1e-13, err_msg=name)
+
+
+@pytest.mark.parametrize("k", [1, 5, 17])
+def test_in_star(k):
+    # leaves -> dangling centre: x_c = (1+dk)/(k+1+dk), x_l = 1/(k+1+dk)
+    g = wl.in_star(k)
+    xc, xl = (1 + D * k) / (k + 1 + D * k), 1 / (k + 1 + D * k)
+    expect = np.array([xc] + [xl] * k)
+    for name, x in all_solvers(g, D).items():
+        np.testing.assert_allclose(x, expect, atol=1e-13, err_msg=name)
+
+
+@pytest.mark.parametrize("k", [1, 5, 17])
+def test_out_star(k):
+    # centre -> dangling leaves: x_c = 1/(k+1+d), x_l = (1+d/k)/(k+1+d)
+    g = wl.out_star(k)
+    expect = np.array([1 / (k + 1 + D)] + [(1 + D / k) / (k + 1 + D)] * k)
+    for name, x in all_solvers(g, D).items():
+        np.testing.assert_allclose(x, expect, atol=1e-13, err_msg=name)
+
+
+@pytest.mark.parametrize("k", [2, 9])
+def test_bi_star(k):
+    # no dangling node: Y sums to one, Y_c = (1+dk)/(N(1+d)), Y_l = (1-d)/N + d Y_c/k
+    g = wl.bi_star(k)
+    n = k + 1
+    yc = (1 + D * k) / (n * (1 + D))
+    expect = np.array([yc] + [(1 - D) / n + D * yc / k] * k)
+    Y, _ = oracle.dense_exact(g, D)
+    np.testing.assert_allclose(Y, expect, atol=1e-15)
+    for name, x in all_solvers(g, D).items():
+        np.testing.assert_allclose(x, expect, atol=1e-13, err_msg=name)
+
+
+def test_d_zero_gives_v():
+    g = wl.random_small(30, 90, seed=3)
+    v = np.random.default_rng(1).random(30)
+    v /= v.sum()
+    for name, x in all_solvers(g, 0.0, v).items():
+        np.testing.assert_allclose(x, v, atol=1e-15, err_msg=name)
+
+
+def test_all_dangling_gives_v():
+    g = wl.from_edges(6, [], [])
+    v = np.array([0.1, 0.2, 0.3, 0.15, 0.05, 0.2])
+    for name, x in all_solvers(g, D, v).items():
+        np.testing.assert_allclose(x, v, atol=1e-15, err_msg=name)
+
+
+@pytest.mark.parametrize("n", [5, 12])
+def test_ppr_on_cycle(n):
+    # V = e_0 on a directed n-cycle: Y_k = (1-d) d^k / (1 - d^n)
+    g = wl.cycle(n)
+    v = np.zeros(n)
+    v[0] = 1.0
+    Y = (1 - D) * D ** np.arange(n) / (1 - D ** n)
+    Yd, _ = oracle.dense_exact(g, D, v)
+    np.testing.assert_allclose(Yd, Y, atol=1e-15)
+    for name, x in all_solvers(g, D, v).items():
+        np.testing.assert_allclose(x, Y / Y.sum(), atol=1e-13, err_msg=name)
+
+
+# ----------------------------------------------- definitions cross-checked
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_renormalised_limit_is_completed_pagerank(seed):
+    """Section 3.4: H_inf / ||H_inf||_1 equals the PageRank of the matrix completed
+    with V on its dangling columns (independent route: eigenvector of A)."""
+    g = wl.random_small(40, 120, seed=seed, p_dangling=0.3)
+    v = np.random.default_rng(seed).random(40)
+    v /= v.sum()
+    x = oracle.dense_exact(g, D, v)[1]
+    np.testing.assert_allclose(x, oracle.completed_pagerank(g, D, v), atol=1e-13)
+
+
+def test_sparse_and_dense_exact_agree():
+    g = wl.random_small(700, 4000, seed=5)
+    np.testing.assert_allclose(oracle.sparse_exact(g, D)[1], oracle.dense_exact(g, D)[1],
+                               atol=1e-14)
+
+
+# -------------------------------------------------- theorems of Section 3
+
+def _partial(g, order, picks, v=None, d=D):
+    return oracle.diter(g, d, 1e-300, order=order, v=v, seed=11, max_picks=picks)
+
+
+@pytest.mark.parametrize("order", ORDERS)
+@pytest.mark.parametrize("picks", [1, 7, 60, 400])
+def test_theorem1_invariant(order, picks):
+    """Theorem 1: H_n + F_n = F_0 + d P H_n, componentwise, for any sequence.
+    Also: the running R of ALGO-REF with the dangling rule (Section 3.4) equals
+    the remaining fluid ||F_n||_1."""
+    g = wl.random_small(50, 160, seed=picks, p_dangling=0.25)
+    r = _partial(g, order, picks)
+    assert r["stats"]["running_r"] == pytest.approx(r["F"].sum(), rel=1e-12)
+    F0 = (1 - D) * np.full(g.n, 1.0 / g.n)
+    lhs = r["H"] + r["F"]
+    rhs = F0 + D * (P_sparse(g) @ r["H"])
+    np.testing.assert_allclose(lhs, rhs, atol=1e-16, rtol=1e-13)
+
+
+@pytest.mark.parametrize("picks", [3, 40, 300])
+def test_theorem2_equality_without_dangling(picks):
+    """Theorem 2: ||S_inf - H_n||_1 = ||F_n||_1/(1-d) when no column of P is zero."""
+    g = wl.random_small(45, 200, seed=picks, p_dangling=0.0)
+    assert g.n_dangling == 0
+    Y, _ = oracle.dense_exact(g, D)
+    for order in ORDERS:
+        r = _partial(g, order, picks)
+        err = np.abs(Y - r["H"]).sum()
+        assert err == pytest.approx(np.abs(r["F"]).sum() / (1 - D), rel=1e-12), order
+
+
+@pytest.mark.parametrize("picks", [3, 40, 300])
+def test_theorem2_bounds_with_dangling(picks):
+    """With dangling nodes ||F||/(1-d) only bounds ||Y - H||_1 (Section 3.4), and
+    Y - (H+F) = dP(I-dP)^{-1}F >= 0 is bounded by d||F||_1/(1-d)."""
+    g = wl.random_small(45, 150, seed=picks, p_dangling=0.3)
+    Y, _ = oracle.dense_exact(g, D)
+    for order in ORDERS:
+        r = _partial(g, order, picks)
+        nf = np.abs(r["F"]).sum()
+        assert np.abs(Y - r["H"]).sum() <= nf / (1 - D) * (1 + 1e-12) + 1e-16
+        gap = Y - (r["H"] + r["F"])
+        assert gap.min() >= -1e-15
+        assert gap.sum() <= D * nf / (1 - D) * (1 + 1e-12) + 1e-16
+
+
+def test_history_increases_to_limit():
+    """Section 3.1: H_n increases componentwise and stays below X = H_inf."""
+    g = wl.random_small(60, 240, seed=9)
+    Y, _ = oracle.dense_exact(g, D)
+    prev = np.zeros(g.n)
+    for picks in [1, 5, 20, 80, 320, 1280, 5120]:
+        H = _partial(g, "rand", picks)["H"]
+        assert np.all(H >= prev - 1e-17)
+        assert np.all(H <= Y + 1e-15)
+        prev = H
+
+
+@pytest.mark.parametrize("order", ["max", "op", "op2"])
+def test_lemma_contraction_for_argmax(order):
+    """Lemma of Section 3.1: with i_n = argmax F, ||F_n|| <= ||F_{n-1}||(1-(1-d)/N).
+    (Checked for MAX; OP/OP2 need not satisfy it, so they are only checked for
+    monotone decrease.)"""
+    g = wl.random_small(35, 120, seed=4)
+    r = oracle.diter(g, D, 1e-300, order=order, max_picks=500, trace_len=500)
+    tr = np.concatenate([[1 - D], r["trace"]])
+    ratio = tr[1:] / tr[:-1]
+    if order == "max":
+        assert np.all(ratio <= 1 - (1 - D) / g.n + 1e-12)
+    else:
+        assert np.all(ratio <= 1 + 1e-12)
+
+
+def test_jacobi_sets_equal_power_series():
+    """All-nodes set steps from F_0 give H_n = S_{n-1} = (1-d) sum_{k<n} d^k P^k V
+    (Section 2.2), which is also MAT-ITER's X_n from X_0 = 0."""
+    g = wl.random_small(80, 300, seed=12)
+    P = P_sparse(g)
+    v = np.full(g.n, 1.0 / g.n)
+    S, term = np.zeros(g.n), (1 - D) * v
+    for n in range(1, 25):
+        S = S + term
+        term = D * (P @ term)
+        H = oracle.diter_sets(g, D, 1e-300, c=0.0, max_rounds=n)["H"]
+        X = oracle.power(g, D, 1e-300, max_iter=n)["X"]
+        np.testing.assert_allclose(H, S, rtol=1e-13, atol=1e-18)
+        np.testing.assert_allclose(X, S, rtol=1e-13, atol=1e-18)
+
+
+def test_set_step_by_hand():
+    # 0->1, 0->2, 1->2, 2 dangling; take {0, 2} with theta between b and min(a, c)
+    g = wl.from_edges(3, [0, 0, 1], [1, 2, 2])
+    a, b, c = 0.5, 0.1, 0.3
+    F, H, taken, st = oracle.set_step(g, D, 0.3, [a, b, c], [1.0, 2.0, 3.0])
+    np.testing.assert_array_equal(taken, [True, False, True])  # F_i >= theta is inclusive
+    np.testing.assert_allclose(F, [0.0, b + D * a / 2, D * a / 2], rtol=1e-15)
+    np.testing.assert_allclose(H, [1.0 + a, 2.0, 3.0 + c], rtol=1e-15)
+    assert st["edges"] == 2 and st["picks"] == 2
+
+
+def test_set_step_keeps_theorem1():
+    g = wl.random_small(200, 900, seed=21)
+    F, H = oracle.init_state(g.n, D)
+    F0 = F.copy()
+    rng = np.random.default_rng(0)
+    for _ in range(30):
+        theta = rng.uniform(0, 2) * F.sum() / g.n
+        F, H, _, _ = oracle.set_step(g, D, theta, F, H)
+    np.testing.assert_allclose(H + F, F0 + D * (P_sparse(g) @ H), rtol=1e-13, atol=1e-18)
+
+
+# --------------------------------------------------- stop rule and orders
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-8])
+def test_order_independence_within_bound(tol):
+    """Every sequence converges to the same limit (Sections 1, 3.2); at residual
+    ||F||_1 < tol each normalised result is within 2d tol/((1-d)||H+F||_1) of x*."""
+    g = wl.random_small(300, 1500, seed=2, p_dangling=0.2)
+    xs = oracle.dense_exact(g, D)[1]
+    for order in ORDERS:
+        r = oracle.diter(g, D, tol, order=order, seed=3)
+        assert r["converged"]
+        nf = r["F"].sum()
+        assert nf < tol
+        bound = 2 * D * nf / ((1 - D) * (r["H"] + r["F"]).sum())
+        assert np.abs(r["x"] - xs).sum() <= bound * (1 + 1e-9) + 1e-15, order
+    for c in [0.0, 0.5, 1.0, 3.0]:
+        r = oracle.diter_sets(g, D, tol, c=c)
+        bound = 2 * D * r["F"].sum() / ((1 - D) * (r["H"] + r["F"]).sum())
+        assert np.abs(r["x"] - xs).sum() <= bound * (1 + 1e-9) + 1e-15, c
+
+
+def test_power_stop_rule_bound():
+    """With X_0 = 0, X_n - X_{n-1} is the Jacobi fluid, so the MAT-ITER result at
+    ||X_n - X_{n-1}||_1 < tol carries the same d tol/(1-d) bound (before
+    normalisation) as the D-iteration."""
+    g = wl.random_small(300, 1500, seed=8)
+    Y, _ = oracle.dense_exact(g, D)
+    for tol in [1e-3, 1e-6, 1e-9]:
+        r = oracle.power(g, D, tol)
+        assert r["converged"] and r["stats"]["residual"] < tol
+        assert np.abs(Y - r["X"]).sum() <= D * r["stats"]["residual"] / (1 - D) * (1 + 1e-9)
+
+
+def test_medium_graph_all_routes():
+    """10k-node power-law graph: sparse LU, MAT-ITER and the threshold D-iteration."""
+    g = wl.recipe("pagerank-10k")
+    xs = oracle.sparse_exact(g, D)[1]
+    np.testing.assert_allclose(oracle.power(g, D, 1e-13)["x"], xs, atol=1e-12)
+    r = oracle.diter_sets(g, D, 1e-12, c=1.0)
+    assert np.abs(r["x"] - xs).sum() < 1e-10
+    r = oracle.diter(g, D, 1e-12, order="sweep")
+    assert np.abs(r["x"] - xs).sum() < 1e-10
+
+
+def test_threshold_variant_uses_fewer_elementary_steps():
+    """Section 4.2's qualitative claim on a power-law graph: threshold rounds reach
+    the same residual with fewer elementary steps than MAT-ITER."""
+    g = wl.recipe("pagerank-10k")
+    p = oracle.power(g, D, 1e-8)
+    s = oracle.diter_sets(g, D, 1e-8, c=1.0)
+    assert s["stats"]["edges"] < p["stats"]["edges"]
