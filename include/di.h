@@ -1,0 +1,237 @@
+/*
+ * di.h -- D-iteration PageRank on AMD MI355X (gfx950): the C ABI of libdi.so.
+ *
+ * Method: D. Hong, "Optimized on-line computation of PageRank algorithm"
+ * (arXiv 1202.6158).  The library solves
+ *
+ *        X = d P X + (1-d) V                               (Section 2.1)
+ *
+ * for a non-negative N x N matrix P whose non-zero columns sum to one (column
+ * i = the out-links of node i, P[j][i] = p(j,i)); zero columns (dangling
+ * nodes) are allowed and are NOT completed (Section 3.4).  V is a normalised
+ * non-negative vector (uniform for PageRank, a seed set for personalised
+ * PageRank), 0 <= d < 1.
+ *
+ * The D-iteration keeps a fluid vector F (F_0 = (1-d)V) and a history H
+ * (H_0 = 0).  Diffusing node i moves F_i into H_i and pushes d F_i p(j,i) to
+ * each child j (the fluid/history recurrences of Section 2.2).  Any order of
+ * diffusions converges to the same limit; this library diffuses, in each
+ * round, every node whose fluid reaches an adaptive threshold (the threshold
+ * variant of Section 4.2), all at once.  Theorem 2 makes ||F||_1 the stopping
+ * residual.  The result is x = (H + F) / ||H + F||_1 (renormalisation of
+ * Section 3.4), or the unnormalised H + F.
+ *
+ * Conventions for every entry point:
+ *  - Nothing throws and nothing aborts.  Each call returns a di_status; on
+ *    failure di_last_error() gives a message (thread-local, valid until the
+ *    next call on the same thread).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is ordered on
+ *    it; a call returns after its results are complete (host outputs written,
+ *    device outputs ready on the stream).
+ *  - Vectors `v` and `x` are host pointers unless DI_DEVICE_PTRS is set in the
+ *    options' flags, in which case they are device pointers (e.g. the
+ *    data_ptr() of a torch tensor on the same device).  Caller-owned.
+ *  - Node ids are 0-based int32; N < 2^31 and nnz < 2^36.
+ */
+#ifndef DI_H
+#define DI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DI_OK = 0,
+  DI_EINVAL = -1,     /* invalid argument (graph, vector, d, tol, seeds ...) */
+  DI_ENOMEM = -2,     /* device allocation failed, or a request exceeds the memory budget */
+  DI_EDEVICE = -3,    /* HIP runtime error, or a non-finite residual */
+  DI_ENOTCONV = -4,   /* max_rounds reached: outputs and stats are still valid (H is a
+                         lower bound of the limit with the reported error bound) */
+  DI_EAGAIN = -5,     /* server: result not ready yet */
+  DI_ECANCELED = -6,  /* server: request was cancelled */
+  DI_EBUSY = -7       /* graph still referenced by a server */
+} di_status;
+
+typedef struct di_graph di_graph;   /* immutable device-resident graph */
+typedef struct di_server di_server; /* continuous-batching PPR server */
+
+/* precision */
+enum {
+  DI_FP32_FLUID = 0, /* fluid F and pushes in fp32; H, residuals, normalisation in fp64 */
+  DI_FP64 = 1        /* everything in fp64 */
+};
+
+/* flags */
+enum {
+  DI_DEVICE_PTRS = 1u, /* v / x / seeds-weights are device pointers */
+  DI_RESUME = 2u       /* di_solve: start from the state passed in di_opts.state_f/state_h */
+};
+
+/* threshold schedule families (Section 4.2 threshold variant; Section 4.3 scores) */
+enum {
+  DI_SCHED_MEAN = 0, /* take i if F_i >= c * R / N_eff (R = remaining fluid) */
+  DI_SCHED_OP2 = 1,  /* take i if F_i/(#out_i+1) >= c * mean of that score (ALGO-OP2) */
+  DI_SCHED_OP = 2    /* take i if F_i/((#in_i+1)(#out_i+1)) >= c * mean (ALGO-OP) */
+};
+
+/* Tuning knobs (all optional; zero = library default). */
+typedef struct di_tune {
+  int32_t schedule;    /* DI_SCHED_* */
+  float c;             /* threshold factor (default 1.0) */
+  int32_t window_log2; /* destination window of the binned scatter: 2^k nodes (8..14) */
+  int32_t check_every; /* rounds between host checks of the device done flag (0 = adaptive) */
+} di_tune;
+
+typedef struct di_opts {
+  double d;           /* damping factor, 0 <= d < 1 */
+  double tol;         /* stop when ||F||_1 < tol (tol > 0) */
+  int32_t precision;  /* DI_FP32_FLUID or DI_FP64 */
+  int32_t normalize;  /* 1: x = (H+F)/||H+F||_1;  0: x = H+F (approximates Y = (1-d)(I-dP)^-1 V) */
+  int64_t max_rounds; /* 0 = 1,000,000 */
+  const di_tune* tune; /* NULL = defaults */
+  uint32_t flags;     /* DI_DEVICE_PTRS | DI_RESUME */
+  uint32_t pad;
+  void* state_f;      /* DI_RESUME: device fluid (float* or double* per precision), in/out */
+  double* state_h;    /* DI_RESUME: device history (double*), in/out */
+} di_opts;
+
+typedef struct di_stats {
+  double residual_l1;  /* ||F||_1 at the stop, summed afresh in fp64 (power: ||x_n - x_n-1||_1) */
+  double err_bound_l1; /* bound on ||x - x*||_1: 2d r/((1-d)||H+F||_1) normalised, d r/(1-d) not */
+  double mass_drift;   /* sum(H) + (sum(F) + d sum_{dangling} H)/(1-d) - sum(V): 0 in exact arithmetic */
+  double seconds;      /* device time of the solve on the stream (HIP events) */
+  int64_t rounds;      /* diffusion rounds (power: matrix products) */
+  int64_t nodes_diffused; /* node diffusions that moved fluid */
+  int64_t edges_diffused; /* elementary steps: out-links used (power: nnz per product) */
+} di_stats;
+
+/* ------------------------------------------------------------------ graph */
+
+/*
+ * Build a device-resident graph from source-ordered CSR (out-links):
+ * the children of node i are col_idx[row_ptr[i] .. row_ptr[i+1]).  Repeated
+ * links and self-loops are allowed and count with multiplicity.
+ *   w == NULL: p(j,i) = 1/outdeg(i) per link (unweighted graph);
+ *   else w[e] >= 0 is the weight of link e, and every non-dangling node's
+ *   weights must sum to 1 within 1e-9 (columns of P, Section 2.1).
+ * row_ptr: int64[n+1], col_idx: int32[nnz], w: double[nnz]; host pointers
+ * (the library copies them; the caller keeps ownership).
+ * Errors: DI_EINVAL if n < 1, nnz < 0, row_ptr[0] != 0, row_ptr not
+ * non-decreasing, row_ptr[n] != nnz, a col_idx out of [0,n), a weight negative
+ * or not finite, or a weight column sum off by more than 1e-9; DI_ENOMEM.
+ */
+di_status di_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                          const double* w, void* stream, di_graph** out);
+di_status di_graph_destroy(di_graph* g); /* DI_EBUSY while a server references it */
+di_status di_graph_info(const di_graph* g, int64_t* n, int64_t* nnz, int64_t* n_dangling);
+
+/* --------------------------------------------------------- single solves */
+
+/*
+ * D-iteration solve (Sections 2.2, 3.4, 4.2).  v: double[n] normalised
+ * personalisation vector (NULL = uniform 1/N); x: double[n] result.
+ * With DI_RESUME the state (opts->state_f, opts->state_h, device arrays of n
+ * entries) replaces the initial F_0 = (1-d)V, H_0 = 0 and receives the final
+ * state; v is then only used for mass_drift.
+ * Errors: DI_EINVAL (d outside [0,1), tol <= 0, v negative / not finite / sum
+ * not within 1e-9 of 1, bad precision), DI_ENOTCONV, DI_EDEVICE, DI_ENOMEM.
+ */
+di_status di_solve(const di_graph* g, const double* v, const di_opts* opts, double* x,
+                   di_stats* stats, void* stream);
+
+/*
+ * Comparator: power iteration X_{n+1} = d P X_n + (1-d) V from X_0 = 0
+ * (MAT-ITER, Sections 2.1 and 4), as a pull (gather) over in-links, without
+ * dangling completion, stopped when ||X_n - X_{n-1}||_1 < tol; x is
+ * normalised at the end when opts->normalize.  precision DI_FP64 gathers
+ * fp64 iterates; DI_FP32_FLUID runs the delta form F_{n+1} = d P F_n with
+ * fp32 F and an fp64 accumulation of X.  Same errors as di_solve.
+ */
+di_status di_power_solve(const di_graph* g, const double* v, const di_opts* opts, double* x,
+                         di_stats* stats, void* stream);
+
+/*
+ * One threshold round on caller-provided device state (the kernel step of a
+ * di_solve round): every node with F_i > 0 and F_i >= theta (compared in
+ * fp64) is taken -- H_i += F_i, F_i = 0 -- and its fluid is pushed,
+ * d F_i p(j,i) to each child j (the set form of the Section 2.2 recurrences).
+ * F: device float[n] (DI_FP32_FLUID) or double[n] (DI_FP64); H: device
+ * double[n].  taken_nodes / taken_edges (host, may be NULL) receive |S| and
+ * the out-links used.
+ */
+di_status di_diffuse_round(const di_graph* g, int32_t precision, double d, double theta,
+                           void* F, double* H, int64_t* taken_nodes, int64_t* taken_edges,
+                           void* stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/*
+ * Personalised PageRank for B seed sets on one graph.  Seed set b is
+ * seeds[seed_ptr[b] .. seed_ptr[b+1]) (non-empty, ids in [0,n), no repeats);
+ * V_b puts weight seed_w[k] on seeds[k] (seed_w NULL = uniform over the set;
+ * otherwise each set's weights must sum to 1 within 1e-9).  opts applies to
+ * every vector (each stops on its own ||F_b||_1 < tol).  x: B x n doubles,
+ * row-major (x[b*n + i]); stats: B entries (may be NULL).  seed_ptr, seeds,
+ * seed_w are host arrays.  DI_ENOTCONV if any vector hit max_rounds.
+ */
+di_status di_solve_batch(const di_graph* g, int32_t B, const int64_t* seed_ptr,
+                         const int32_t* seeds, const double* seed_w, const di_opts* opts,
+                         double* x, di_stats* stats, void* stream);
+
+/* ----------------------------------------------------------------- server */
+
+typedef struct di_server_opts {
+  int64_t hbm_budget_bytes; /* device bytes the server may hold for request state (0 = 32 GiB) */
+  int32_t max_slots;        /* concurrent requests on the device (0 = 256) */
+  int32_t topk;             /* results kept per request (0 = 100) */
+  int32_t precision;        /* DI_FP32_FLUID or DI_FP64 */
+  int32_t pad;
+  const di_tune* tune;      /* NULL = defaults */
+} di_server_opts;
+
+typedef struct di_result {
+  uint64_t req_id;
+  int32_t status;          /* DI_OK, DI_ENOTCONV, DI_ECANCELED, DI_EDEVICE */
+  int32_t k;               /* entries filled in top_ids / top_x */
+  int32_t top_ids[1024];   /* highest-ranked nodes, best first (ties: lower id first) */
+  double top_x[1024];      /* their normalised scores */
+  double residual_l1, err_bound_l1;
+  double t_submit, t_admit, t_done; /* seconds on the server's clock */
+  int64_t rounds, edges_diffused;
+} di_result;
+
+typedef struct di_server_metrics {
+  int64_t submitted, admitted, completed, cancelled, queued, active;
+  int64_t hbm_in_use, hbm_budget;
+  double p50_latency_s, p99_latency_s, qps;
+} di_server_metrics;
+
+/* Create a server with its own scheduler thread and HIP stream. */
+di_status di_server_create(const di_server_opts* opts, di_server** out);
+/* Register a resident graph (not copied; must outlive the server). */
+di_status di_server_add_graph(di_server* s, const di_graph* g, int32_t* graph_id);
+/* Enqueue a PPR request (thread-safe, non-blocking).  seeds (and w, NULL =
+   uniform) are host arrays copied at submit.  DI_EINVAL on bad input,
+   DI_ENOMEM if one request can never fit the budget. */
+di_status di_server_submit(di_server* s, int32_t graph_id, int32_t n_seeds, const int32_t* seeds,
+                           const double* w, double d, double tol, uint64_t* req_id);
+/* DI_EAGAIN while pending; otherwise fills *out and forgets the request. */
+di_status di_server_poll(di_server* s, uint64_t req_id, di_result* out);
+/* Block up to timeout_s (< 0 = forever); DI_EAGAIN on timeout. */
+di_status di_server_wait(di_server* s, uint64_t req_id, double timeout_s, di_result* out);
+di_status di_server_cancel(di_server* s, uint64_t req_id);
+di_status di_server_stats(di_server* s, di_server_metrics* out);
+di_status di_server_destroy(di_server* s);
+
+/* ------------------------------------------------------------------ misc */
+
+const char* di_last_error(void);
+const char* di_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DI_H */

@@ -1,0 +1,179 @@
+// Internal declarations shared by the libdi translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/di.h"
+
+namespace di {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string& msg);
+const std::string& last_error_ref();
+
+struct Fail {
+  di_status st;
+};
+
+#define DI_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::di::set_error(std::string(#call) + ": " + hipGetErrorString(e_));              \
+      throw ::di::Fail{e_ == hipErrorOutOfMemory ? DI_ENOMEM : DI_EDEVICE};            \
+    }                                                                                  \
+  } while (0)
+
+#define DI_REQUIRE(cond, msg)                   \
+  do {                                          \
+    if (!(cond)) {                              \
+      ::di::set_error(msg);                     \
+      throw ::di::Fail{DI_EINVAL};              \
+    }                                           \
+  } while (0)
+
+// Runs f, mapping di::Fail and std exceptions to a status.
+template <typename Fn>
+di_status guarded(Fn&& f) {
+  try {
+    f();
+    return DI_OK;
+  } catch (const Fail& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return DI_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return DI_EDEVICE;
+  }
+}
+
+// Owning device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    if (n <= bytes && p) return;
+    release();
+    if (n == 0) n = 16;
+    DI_HIP(hipMalloc(&p, n));
+    bytes = n;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void alloc(size_t n) {
+    if (n <= bytes && p) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    DI_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+    bytes = n;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// --------------------------------------------------------------- constants
+
+constexpr int kBlock = 256;        // threads per workgroup of the streaming kernels
+constexpr int kBatch = 512;        // frontier entries staged per expand batch
+constexpr int64_t kMaxNnz = 1ll << 36;  // links per graph
+constexpr int kMaxBuckets = 4096;  // destination windows per solve
+constexpr int kPullRows = 256;     // rows per pull block (one per thread)
+constexpr int kPullNnz = 2048;     // staged in-links per pull block
+
+// ----------------------------------------------------------------- graph
+
+struct Workspace;
+
+struct Graph {
+  int64_t n = 0, m = 0, n_dangling = 0;
+  bool weighted = false;
+  int device = 0;
+  // source-CSR (push side)
+  DevBuf row_ptr;  // int64[n+1]
+  DevBuf deg;      // int32[n] out-degree
+  DevBuf col;      // int32[m]
+  DevBuf w;        // double[m] (weighted graphs)
+  DevBuf indeg;    // int32[n] in-degree (ALGO-OP score)
+  // destination-CSR (pull side) and the window layout derived from it
+  DevBuf in_ptr;   // int64[n+1]
+  DevBuf in_src;   // int32[m]
+  DevBuf in_w;     // double[m] (weighted graphs)
+  DevBuf pull_blk; // int32[npull+1]: first row of each pull block
+  int64_t npull = 0;
+  // reusable solve workspaces
+  std::mutex ws_mu;
+  std::vector<Workspace*> ws_free;
+  int servers = 0;
+  ~Graph();
+};
+
+// Window size (log2 nodes) of the binned scatter for a graph of n nodes: about
+// 512 windows, the round kernel's LDS (fp64 window + per-window tables) within
+// the workgroup limit, at most kMaxBuckets windows (-1 if impossible).
+int window_log2_for(int64_t n, int requested);
+// LDS bytes of the round kernel's dynamic part for window 2^wlog and nb windows.
+size_t round_lds_bytes(int wlog, int nb);
+
+// Workspaces (defined in diter.hip).
+Workspace* acquire_workspace(Graph* g, int precision, int wlog);
+void release_workspace(Graph* g, Workspace* ws);
+void destroy_workspace(Workspace* ws);
+
+// Validation helpers.
+void validate_d_tol(const di_opts* o);
+void validate_vector(const double* v, int64_t n, const char* what);
+
+// Timing helper: records events around a region on a stream.
+struct EventTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit EventTimer(hipStream_t st) : s(st) {
+    DI_HIP(hipEventCreate(&a));
+    DI_HIP(hipEventCreate(&b));
+    DI_HIP(hipEventRecord(a, s));
+  }
+  double stop() {
+    DI_HIP(hipEventRecord(b, s));
+    DI_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    DI_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms * 1e-3;
+  }
+  ~EventTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+}  // namespace di
+
+struct di_graph : di::Graph {};

@@ -1,0 +1,314 @@
+// Power-iteration comparator (MAT-ITER, Sections 2.1 and 4) on gfx950.
+//
+//   X_{n+1} = d P X_n + (1-d) V,  X_0 = 0,  stop when ||X_n - X_{n-1}||_1 < tol,
+//
+// without dangling completion; the result is normalised at the end (the
+// renormalisation that replaces completion, Section 4.2).  Each product is a
+// pull over in-links: row blocks of up to kPullRows rows / kPullNnz links stage
+// the gathered source values in LDS (coalesced index reads), one thread then
+// sums each row; a row with more in-links than a block holds is reduced by
+// the whole workgroup.  The iterate is stored twice, as X and as X/outdeg (the
+// value every out-link carries), so a link costs one gather.
+//
+// precision DI_FP64: fp64 iterate.  DI_FP32_FLUID: the delta form
+//   F_0 = (1-d)V, F_{n+1} = d P F_n (fp32 gather), X_{n+1} = X_n + F_{n+1} (fp64),
+// whose increments are the Jacobi fluid of the D-iteration.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "kernels.h"
+
+namespace di {
+
+struct PowCtl {
+  int done_at;   // -1 while running; else k: X_k met the stop rule
+  int reason;    // 1 converged, 2 non-finite, 3 max iterations
+  double res;    // ||X_k - X_{k-1}||_1 at the stop
+  double sum;    // flush sum
+  double pad[5];
+  double acc[3][256];  // residual partials of products k (slot k % 3), spread over 256 slots
+};
+
+template <typename G>  // G: gathered type (double, or float for the delta form)
+struct PowArgs {
+  int64_t n;
+  const int64_t* in_ptr;
+  const int32_t* in_src;
+  const double* in_w;
+  const int32_t* deg;
+  const int32_t* blk;
+  const double* v;
+  double d, tol;
+  int64_t max_iter;
+  double* x[2];  // iterate (fp64); the delta form accumulates into x[0]
+  G* xs[2];      // value carried by each out-link
+  PowCtl* ctl;
+  int delta;
+};
+
+template <typename G>
+__global__ __launch_bounds__(kBlock) void k_pow_init(PowArgs<G> a) {
+  const double u = 1.0 / (double)a.n;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * kBlock) {
+    if (a.delta) {
+      // F_0 = (1-d)V is the first increment: X_1 = F_0.
+      const double f = (1.0 - a.d) * (a.v ? a.v[i] : u);
+      const int dg = a.deg[i];
+      a.x[0][i] = f;
+      a.xs[0][i] = (G)(dg > 0 ? (a.in_w ? f : f / dg) : 0.0);
+    } else {
+      a.x[0][i] = 0.0;
+      a.xs[0][i] = (G)0;
+    }
+  }
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < 3 * 256; k += kBlock) (&a.ctl->acc[0][0])[k] = 0.0;
+    if (threadIdx.x == 0) {
+      a.ctl->done_at = -1;
+      a.ctl->reason = 0;
+      a.ctl->res = 0.0;
+      a.ctl->sum = 0.0;
+    }
+  }
+}
+
+// Product k: X_{k+1} = d P X_k + (1-d) V (delta form: F_{k+1} = d P F_k,
+// X += F_{k+1}).  Every workgroup first reduces the residual of product k-1
+// from its 256 slots (same order everywhere, so all agree on the stop).
+template <typename G, bool kWeighted>
+__global__ __launch_bounds__(kBlock) void k_pull(PowArgs<G> a, int k) {
+  PowCtl* ctl = a.ctl;
+  if (__hip_atomic_load(&ctl->done_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
+  __shared__ double s_val[kPullNnz];
+  __shared__ double s_red[kBlock / 64];
+  if (k >= 1) {
+    const double res = block_sum(ctl->acc[(k - 1) % 3][threadIdx.x], s_red);
+    int reason = 0;
+    if (!isfinite(res)) reason = 2;
+    else if (res < a.tol) reason = 1;
+    else if ((int64_t)k >= a.max_iter) reason = 3;
+    if (reason) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->res = res;
+        ctl->reason = reason;
+        ctl->done_at = k;
+      }
+      return;
+    }
+  }
+  if (blockIdx.x == 0) ctl->acc[(k + 1) % 3][threadIdx.x] = 0.0;  // for product k+1
+  const int cur = k & 1, nxt = cur ^ 1;
+  const G* __restrict__ xs = a.xs[cur];
+  G* __restrict__ ys = a.xs[nxt];
+  const int r0 = a.blk[blockIdx.x], r1 = a.blk[blockIdx.x + 1];
+  const int64_t e0 = a.in_ptr[r0], e1 = a.in_ptr[r1];
+  const double u = 1.0 / (double)a.n;
+  double diff = 0.0;
+  auto finish_row = [&](int r, double gathered) {
+    const double base = a.delta ? 0.0 : (1.0 - a.d) * (a.v ? a.v[r] : u);
+    const double y = base + a.d * gathered;  // X_{k+1} (or F_{k+1} in delta form)
+    const int dg = a.deg[r];
+    const double carry = dg > 0 ? (kWeighted ? y : y / dg) : 0.0;
+    if (a.delta) {
+      diff += fabs(y);
+      a.x[0][r] += y;
+    } else {
+      diff += fabs(y - a.x[cur][r]);
+      a.x[nxt][r] = y;
+    }
+    ys[r] = (G)carry;
+  };
+  if (r1 - r0 == 1 && e1 - e0 > kPullNnz) {
+    double acc = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+      double t = (double)xs[a.in_src[e]];
+      if (kWeighted) t *= a.in_w[e];
+      acc += t;
+    }
+    acc = block_sum(acc, s_red);
+    if (threadIdx.x == 0) finish_row(r0, acc);
+  } else {
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+      double t = (double)xs[a.in_src[e]];
+      if (kWeighted) t *= a.in_w[e];
+      s_val[e - e0] = t;
+    }
+    __syncthreads();
+    const int r = r0 + threadIdx.x;
+    if (r < r1) {
+      double acc = 0.0;
+      const int64_t b = a.in_ptr[r] - e0, c = a.in_ptr[r + 1] - e0;
+      for (int64_t q = b; q < c; ++q) acc += s_val[q];
+      finish_row(r, acc);
+    }
+  }
+  diff = block_sum(diff, s_red);
+  if (threadIdx.x == 0 && diff != 0.0) unsafeAtomicAdd(&ctl->acc[k % 3][blockIdx.x & 255], diff);
+}
+
+static_assert(kBlock == 256, "one residual slot per thread");
+
+__global__ __launch_bounds__(kBlock) void k_pow_zero(double* __restrict__ slots) {
+  slots[threadIdx.x] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pow_sum(int64_t n, const double* __restrict__ x,
+                                                    double* __restrict__ slots) {
+  __shared__ double s_red[kBlock / 64];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    s += x[i];
+  s = block_sum(s, s_red);
+  if (threadIdx.x == 0) unsafeAtomicAdd(&slots[blockIdx.x & 255], s);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pow_sum_reduce(double* __restrict__ slots, PowCtl* ctl) {
+  __shared__ double s_red[kBlock / 64];
+  const double s = block_sum(slots[threadIdx.x], s_red);
+  if (threadIdx.x == 0) ctl->sum = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pow_write(int64_t n, const double* __restrict__ x,
+                                                      const PowCtl* ctl, int normalize,
+                                                      double* __restrict__ out) {
+  const double s = normalize ? ctl->sum : 1.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    out[i] = x[i] / s;
+}
+
+struct PowWorkspace {
+  DevBuf x0, x1, xs0, xs1, v, out, ctl;
+  PinnedBuf hctl;
+};
+
+template <typename G>
+static di_status power_impl(Graph* g, const double* v, const di_opts* o, double* x,
+                            di_stats* st, hipStream_t s) {
+  const bool dev = (o->flags & DI_DEVICE_PTRS) != 0;
+  const bool delta = std::is_same<G, float>::value;
+  const int64_t n = g->n;
+  const int64_t max_iter = o->max_rounds > 0 ? o->max_rounds : 1000000;
+  if (v && !dev) validate_vector(v, n, "v");
+  PowWorkspace ws;
+  ws.x0.alloc(n * 8);
+  ws.x1.alloc(n * 8);
+  ws.xs0.alloc(n * sizeof(G));
+  ws.xs1.alloc(n * sizeof(G));
+  ws.ctl.alloc(sizeof(PowCtl));
+  ws.hctl.alloc(sizeof(PowCtl));
+  const double* vdev = nullptr;
+  if (v) {
+    if (dev) vdev = v;
+    else {
+      ws.v.alloc(n * 8);
+      DI_HIP(hipMemcpyAsync(ws.v.p, v, n * 8, hipMemcpyHostToDevice, s));
+      vdev = ws.v.as<double>();
+    }
+  }
+  PowArgs<G> a;
+  memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.in_ptr = g->in_ptr.as<int64_t>();
+  a.in_src = g->in_src.as<int32_t>();
+  a.in_w = g->weighted ? g->in_w.as<double>() : nullptr;
+  a.deg = g->deg.as<int32_t>();
+  a.blk = g->pull_blk.as<int32_t>();
+  a.v = vdev;
+  a.d = o->d;
+  a.tol = o->tol;
+  a.max_iter = max_iter;
+  a.x[0] = ws.x0.as<double>();
+  a.x[1] = ws.x1.as<double>();
+  a.xs[0] = ws.xs0.as<G>();
+  a.xs[1] = ws.xs1.as<G>();
+  a.ctl = ws.ctl.as<PowCtl>();
+  a.delta = delta ? 1 : 0;
+  const int grid_n = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 2048));
+  EventTimer timer(s);
+  k_pow_init<G><<<grid_n, kBlock, 0, s>>>(a);
+  DI_HIP(hipGetLastError());
+  PowCtl* h = ws.hctl.as<PowCtl>();
+  int k = 0;
+  int chunk = 16;
+  for (;;) {
+    for (int i = 0; i < chunk; ++i, ++k) {
+      if (g->weighted) k_pull<G, true><<<(int)g->npull, kBlock, 0, s>>>(a, k);
+      else k_pull<G, false><<<(int)g->npull, kBlock, 0, s>>>(a, k);
+      DI_HIP(hipGetLastError());
+    }
+    DI_HIP(hipMemcpyAsync(h, ws.ctl.p, sizeof(PowCtl), hipMemcpyDeviceToHost, s));
+    DI_HIP(hipStreamSynchronize(s));
+    if (h->done_at >= 0) break;
+    // ||X_k - X_{k-1}||_1 decays by about d per product: plan the rest.
+    chunk = 16;
+    if (o->d > 0 && o->d < 1) {
+      double res = 0;
+      for (int q = 0; q < 256; ++q) res += h->acc[(k - 1) % 3][q];
+      if (res > 0 && res > o->tol)
+        chunk = std::max(2, std::min(64, (int)std::ceil(std::log(o->tol / res) / std::log(o->d)) + 1));
+    }
+  }
+  const int K = h->done_at;  // X_K is the answer
+  const double* xr = delta ? a.x[0] : a.x[K & 1];
+  double* out = dev ? x : nullptr;
+  if (x && !dev) {
+    ws.out.alloc(n * 8);
+    out = ws.out.as<double>();
+  }
+  double* slots = &a.ctl->acc[0][0];
+  k_pow_zero<<<1, kBlock, 0, s>>>(slots);
+  DI_HIP(hipGetLastError());
+  k_pow_sum<<<grid_n, kBlock, 0, s>>>(n, xr, slots);
+  DI_HIP(hipGetLastError());
+  k_pow_sum_reduce<<<1, kBlock, 0, s>>>(slots, a.ctl);
+  DI_HIP(hipGetLastError());
+  if (x) {
+    k_pow_write<<<grid_n, kBlock, 0, s>>>(n, xr, a.ctl, o->normalize, out);
+    DI_HIP(hipGetLastError());
+  }
+  const double secs = timer.stop();
+  if (x && !dev) DI_HIP(hipMemcpyAsync(x, out, n * 8, hipMemcpyDeviceToHost, s));
+  DI_HIP(hipMemcpyAsync(h, ws.ctl.p, sizeof(PowCtl), hipMemcpyDeviceToHost, s));
+  DI_HIP(hipStreamSynchronize(s));
+  if (st) {
+    const double d = o->d, r = h->res, S = h->sum;
+    st->residual_l1 = r;
+    st->err_bound_l1 = o->normalize ? (S > 0 ? 2.0 * d * r / ((1.0 - d) * S) : 0.0) : d * r / (1.0 - d);
+    st->mass_drift = 0.0;
+    st->seconds = secs;
+    st->rounds = K + (delta ? 1 : 0);
+    st->nodes_diffused = (int64_t)K * n;
+    st->edges_diffused = (int64_t)K * g->m;
+  }
+  if (h->reason == 2) {
+    set_error("non-finite residual");
+    return DI_EDEVICE;
+  }
+  if (h->reason == 3) {
+    set_error("max_rounds reached before ||X_n - X_n-1||_1 < tol");
+    return DI_ENOTCONV;
+  }
+  return DI_OK;
+}
+
+}  // namespace di
+
+using namespace di;
+
+extern "C" di_status di_power_solve(const di_graph* gc, const double* v, const di_opts* opts,
+                                    double* x, di_stats* stats, void* stream) {
+  di_status rc = DI_OK;
+  di_status g = guarded([&] {
+    DI_REQUIRE(gc != nullptr, "graph is NULL");
+    validate_d_tol(opts);
+    Graph* g = const_cast<di_graph*>(gc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = opts->precision == DI_FP64 ? power_impl<double>(g, v, opts, x, stats, s)
+                                    : power_impl<float>(g, v, opts, x, stats, s);
+  });
+  return g != DI_OK ? g : rc;
+}

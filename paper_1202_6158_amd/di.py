@@ -1,0 +1,371 @@
+"""ctypes binding of libdi.so (argument marshalling only).
+
+Every step of a solve runs in the library's HIP kernels; this module converts
+Python arguments into the C structures of include/di.h, passes torch device
+tensors as raw pointers (with DI_DEVICE_PTRS) together with torch's current
+HIP stream, and raises :class:`DiError` for a non-OK status.  There is no
+fallback: if libdi.so is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdi.so not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "or `python paper_1202_6158_amd/build.py` (expected at %s)" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------------ constants
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EAGAIN, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+FP32_FLUID, FP64 = 0, 1
+DEVICE_PTRS, RESUME = 1, 2
+SCHED_MEAN, SCHED_OP2, SCHED_OP = 0, 1, 2
+PRECISION = {"fp32": FP32_FLUID, "fp64": FP64, FP32_FLUID: FP32_FLUID, FP64: FP64}
+SCHEDULE = {"mean": SCHED_MEAN, "op2": SCHED_OP2, "op": SCHED_OP}
+STATUS_NAMES = {OK: "DI_OK", EINVAL: "DI_EINVAL", ENOMEM: "DI_ENOMEM", EDEVICE: "DI_EDEVICE",
+                ENOTCONV: "DI_ENOTCONV", EAGAIN: "DI_EAGAIN", ECANCELED: "DI_ECANCELED",
+                EBUSY: "DI_EBUSY"}
+
+
+class DiError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+        self.message = message
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("c", ctypes.c_float),
+                ("window_log2", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_double), ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("normalize", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
+                ("tune", ctypes.POINTER(Tune)), ("flags", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("state_f", ctypes.c_void_p), ("state_h", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("residual_l1", ctypes.c_double), ("err_bound_l1", ctypes.c_double),
+                ("mass_drift", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("rounds", ctypes.c_int64), ("nodes_diffused", ctypes.c_int64),
+                ("edges_diffused", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("topk", ctypes.c_int32), ("precision", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("tune", ctypes.POINTER(Tune))]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("status", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("top_ids", ctypes.c_int32 * 1024), ("top_x", ctypes.c_double * 1024),
+                ("residual_l1", ctypes.c_double), ("err_bound_l1", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("rounds", ctypes.c_int64),
+                ("edges_diffused", ctypes.c_int64)]
+
+    def as_dict(self):
+        k = self.k
+        return {"req_id": self.req_id, "status": self.status,
+                "top_ids": np.array(self.top_ids[:k], dtype=np.int32),
+                "top_x": np.array(self.top_x[:k]), "residual_l1": self.residual_l1,
+                "err_bound_l1": self.err_bound_l1, "t_submit": self.t_submit,
+                "t_admit": self.t_admit, "t_done": self.t_done, "rounds": self.rounds,
+                "edges_diffused": self.edges_diffused}
+
+
+class ServerMetrics(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("hbm_in_use", ctypes.c_int64), ("hbm_budget", ctypes.c_int64),
+                ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+                ("qps", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "di_graph_create": [ctypes.c_int64, ctypes.c_int64, _P, _P, _P, _P, _P],
+    "di_graph_destroy": [_P],
+    "di_graph_info": [_P, _P, _P, _P],
+    "di_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
+    "di_power_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
+    "di_diffuse_round": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P],
+    "di_solve_batch": [_P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _P],
+    "di_server_create": [ctypes.POINTER(ServerOpts), _P],
+    "di_server_add_graph": [_P, _P, _P],
+    "di_server_submit": [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_double,
+                         ctypes.c_double, _P],
+    "di_server_poll": [_P, ctypes.c_uint64, ctypes.POINTER(Result)],
+    "di_server_wait": [_P, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(Result)],
+    "di_server_cancel": [_P, ctypes.c_uint64],
+    "di_server_stats": [_P, ctypes.POINTER(ServerMetrics)],
+    "di_server_destroy": [_P],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.di_last_error.restype = ctypes.c_char_p
+_lib.di_last_error.argtypes = []
+_lib.di_version.restype = ctypes.c_char_p
+_lib.di_version.argtypes = []
+
+EXPORTED = sorted(list(_SIGS) + ["di_last_error", "di_version"])
+
+
+def last_error() -> str:
+    return _lib.di_last_error().decode()
+
+
+def version() -> str:
+    return _lib.di_version().decode()
+
+
+def _check(rc: int, allow=()):
+    if rc != OK and rc not in allow:
+        raise DiError(rc, last_error())
+    return rc
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data)
+    return ctypes.c_void_p(a.data_ptr())
+
+
+def make_tune(schedule="mean", c=1.0, window_log2=0, check_every=0) -> Tune:
+    return Tune(SCHEDULE.get(schedule, schedule), float(c), int(window_log2), int(check_every))
+
+
+def make_opts(d=0.85, tol=1e-8, precision="fp32", normalize=True, max_rounds=0, tune=None,
+              flags=0) -> Opts:
+    o = Opts()
+    o.d = float(d)
+    o.tol = float(tol)
+    o.precision = PRECISION[precision]
+    o.normalize = 1 if normalize else 0
+    o.max_rounds = int(max_rounds)
+    o.tune = ctypes.pointer(tune) if tune is not None else None
+    o.flags = int(flags)
+    return o
+
+
+class Graph:
+    """A device-resident graph (di_graph_create).  `g` is any object with n,
+    row_ptr (int64[n+1]) and col_idx (int32[nnz]); w optional (double[nnz])."""
+
+    def __init__(self, g=None, *, n=None, row_ptr=None, col_idx=None, w=None, stream=None):
+        if g is not None:
+            n, row_ptr, col_idx = g.n, g.row_ptr, g.col_idx
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        self.w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        self.n = int(n)
+        self.nnz = int(self.row_ptr[-1]) if len(self.row_ptr) else 0
+        self._h = ctypes.c_void_p()
+        st = _stream(stream) if stream is not None else None
+        _check(_lib.di_graph_create(self.n, len(self.col_idx), _ptr(self.row_ptr),
+                                    _ptr(self.col_idx) if len(self.col_idx) else None,
+                                    _ptr(self.w), st, ctypes.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n, m, dg = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.di_graph_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(dg)))
+        return {"n": n.value, "nnz": m.value, "dangling": dg.value}
+
+    def close(self):
+        if self._h:
+            _check(_lib.di_graph_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self._h:
+                _lib.di_graph_destroy(self._h)
+        except Exception:
+            pass
+
+
+def _device_vec(v, n):
+    """torch float64 device tensor for v (or None)."""
+    if v is None:
+        return None
+    torch = _torch()
+    if isinstance(v, np.ndarray):
+        v = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
+    assert v.dtype == torch.float64 and v.is_cuda and v.numel() == n
+    return v.contiguous()
+
+
+def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=True,
+          max_rounds=0, tune=None, out=None, state=None, stream=None, allow_notconv=False):
+    """D-iteration solve on the device.  v: None (uniform), numpy or torch cuda
+    float64[n].  Returns (x: torch cuda float64[n], stats dict).  With
+    state=(F, H) (torch cuda tensors, F float32/float64 per precision, H
+    float64) the solve resumes from and updates that state."""
+    torch = _torch()
+    n = graph.n
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
+    vd = _device_vec(v, n)
+    flags = DEVICE_PTRS
+    o = make_opts(d, tol, precision, normalize, max_rounds, tune, flags)
+    if state is not None:
+        o.flags |= RESUME
+        o.state_f = state[0].data_ptr()
+        o.state_h = state[1].data_ptr()
+    st = Stats()
+    rc = _lib.di_solve(graph.handle, _ptr(vd), ctypes.byref(o), _ptr(x), ctypes.byref(st),
+                       _stream(stream))
+    _check(rc, allow=(ENOTCONV,) if allow_notconv else ())
+    s = st.as_dict()
+    s["status"] = rc
+    return x, s
+
+
+def power_solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp64", normalize=True,
+                max_rounds=0, out=None, stream=None, allow_notconv=False):
+    """Power-iteration comparator (pull SpMV) on the device."""
+    torch = _torch()
+    n = graph.n
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
+    vd = _device_vec(v, n)
+    o = make_opts(d, tol, precision, normalize, max_rounds, None, DEVICE_PTRS)
+    st = Stats()
+    rc = _lib.di_power_solve(graph.handle, _ptr(vd), ctypes.byref(o), _ptr(x), ctypes.byref(st),
+                             _stream(stream))
+    _check(rc, allow=(ENOTCONV,) if allow_notconv else ())
+    s = st.as_dict()
+    s["status"] = rc
+    return x, s
+
+
+def diffuse_round(graph: Graph, F, H, theta: float, d=0.85, stream=None):
+    """One threshold round in place on device tensors F (float32 or float64)
+    and H (float64).  Returns (taken_nodes, taken_edges)."""
+    torch = _torch()
+    prec = FP64 if F.dtype == torch.float64 else FP32_FLUID
+    assert H.dtype == torch.float64 and F.is_cuda and H.is_cuda
+    tn, te = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.di_diffuse_round(graph.handle, prec, float(d), float(theta), _ptr(F), _ptr(H),
+                                 ctypes.byref(tn), ctypes.byref(te), _stream(stream)))
+    return tn.value, te.value
+
+
+def solve_batch(graph: Graph, seed_ptr, seeds, seed_w=None, d=0.85, tol=1e-6, precision="fp32",
+                normalize=True, max_rounds=0, tune=None, out=None, stream=None,
+                allow_notconv=False):
+    """Batched personalised PageRank.  seed_ptr int64[B+1], seeds int32, seed_w
+    float64 or None (host arrays).  Returns (x: torch cuda float64[B, n],
+    list of per-vector stats dicts)."""
+    torch = _torch()
+    seed_ptr = np.ascontiguousarray(seed_ptr, dtype=np.int64)
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+    sw = None if seed_w is None else np.ascontiguousarray(seed_w, dtype=np.float64)
+    B = len(seed_ptr) - 1
+    x = out if out is not None else torch.empty((B, graph.n), dtype=torch.float64, device="cuda")
+    o = make_opts(d, tol, precision, normalize, max_rounds, tune, DEVICE_PTRS)
+    st = (Stats * max(B, 1))()
+    rc = _lib.di_solve_batch(graph.handle, B, _ptr(seed_ptr), _ptr(seeds), _ptr(sw),
+                             ctypes.byref(o), _ptr(x), st, _stream(stream))
+    _check(rc, allow=(ENOTCONV,) if allow_notconv else ())
+    return x, [st[b].as_dict() for b in range(B)]
+
+
+class Server:
+    """Continuous-batching personalised PageRank server (di_server_*)."""
+
+    def __init__(self, hbm_budget_bytes=0, max_slots=0, topk=0, precision="fp32", tune=None):
+        o = ServerOpts()
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.max_slots = int(max_slots)
+        o.topk = int(topk)
+        o.precision = PRECISION[precision]
+        self._tune = tune
+        o.tune = ctypes.pointer(tune) if tune is not None else None
+        self._h = ctypes.c_void_p()
+        _check(_lib.di_server_create(ctypes.byref(o), ctypes.byref(self._h)))
+        self._graphs = []
+
+    def add_graph(self, graph: Graph) -> int:
+        gid = ctypes.c_int32()
+        _check(_lib.di_server_add_graph(self._h, graph.handle, ctypes.byref(gid)))
+        self._graphs.append(graph)
+        return gid.value
+
+    def submit(self, graph_id: int, seeds, w=None, d=0.85, tol=1e-6) -> int:
+        seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        rid = ctypes.c_uint64()
+        _check(_lib.di_server_submit(self._h, int(graph_id), len(seeds), _ptr(seeds), _ptr(w),
+                                     float(d), float(tol), ctypes.byref(rid)))
+        return rid.value
+
+    def poll(self, req_id: int):
+        r = Result()
+        rc = _lib.di_server_poll(self._h, req_id, ctypes.byref(r))
+        if rc == EAGAIN:
+            return None
+        _check(rc)
+        return r.as_dict()
+
+    def wait(self, req_id: int, timeout_s: float = -1.0):
+        r = Result()
+        rc = _lib.di_server_wait(self._h, req_id, float(timeout_s), ctypes.byref(r))
+        if rc == EAGAIN:
+            return None
+        _check(rc)
+        return r.as_dict()
+
+    def cancel(self, req_id: int):
+        _check(_lib.di_server_cancel(self._h, req_id))
+
+    def stats(self):
+        m = ServerMetrics()
+        _check(_lib.di_server_stats(self._h, ctypes.byref(m)))
+        return m.as_dict()
+
+    def close(self):
+        if self._h:
+            _check(_lib.di_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
