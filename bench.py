@@ -1,0 +1,323 @@
+#!/usr/bin/env python3
+"""Benchmark: D-iteration PageRank on one MI355X (gfx950).
+
+One step = one D-iteration solve of the workload graph (uniform V, d = 0.85)
+from F_0 = (1-d)V to ||F||_1 < tol, with the result normalised, inputs already
+resident in HBM.  Prints ONE JSON line with:
+
+  value           solves per second (whole job, one GPU)
+  roofline        the round kernel: algorithmic bytes per launch (4 B per node
+                  scanned, 52 B per node taken, 12 B per link pushed for fp32
+                  fluid; 8 / 64 / 20 B for fp64) over its average launch
+                  duration, timed with HIP events on the solve's stream
+  comparator      the GPU power iteration (pull) on the same graph and stop rule
+  cpu_baseline    the CPU oracle's sequential D-iteration on the host
+  ppr_batch       batched personalised PageRank (256 seed sets, 1e-6)
+  serve           the continuous-batching server on a short Poisson stream
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("time to L1 residual 1e-8 & edges diffused/s vs GPU power iter; "
+          "PPR queries/s, p50/p99")
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "round_kernel_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1202_6158_amd", "csrc", f)
+                  for f in ("diter.hip", "kernels.h", "internal.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n, st, precision):
+    """Bytes the D-iteration must move for one solve (scan of F per round,
+    per taken node, per pushed link), excluding the final flush."""
+    if precision == "fp64":
+        return 8 * n * st["rounds"] + 64 * st["nodes_diffused"] + 20 * st["edges_diffused"]
+    return 4 * n * st["rounds"] + 52 * st["nodes_diffused"] + 12 * st["edges_diffused"]
+
+
+def measured_traffic(launches_per_solve):
+    """HBM bytes per round-kernel launch from the committed counter summary,
+    or None when absent or taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return (t["fetch_kib_per_dispatch"] + t["write_kib_per_dispatch"]) * 1024.0 / t["copy_factor"]
+
+
+def cpu_baseline(g, d, tol, budget_s):
+    """The oracle's sequential D-iteration (threshold sweeps) on the host."""
+    import oracle
+    oracle.build(force=False)
+    runs, t0 = 0, time.perf_counter()
+    while True:
+        r = oracle.diter(g, d, tol, order="sweep", c=1.0)
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or runs >= 20:
+            break
+    return {"value": runs / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full solve(s) of the benchmark graph to ||F||_1 < %g by the oracle's "
+                      "sequential threshold-sweep D-iteration (fp64, one thread), %.1f s" %
+                      (runs, tol, el),
+            "edges_per_s": r["stats"]["edges"] / (el / runs)}
+
+
+COPY_MIB = 1024
+
+
+def copy_calibration(mib=COPY_MIB):
+    """A plain device copy of known size (the runtime's copy kernel), whose
+    counter readings scale FETCH_SIZE / WRITE_SIZE into HBM bytes.  A write of
+    another buffer of the same size first evicts the source from the 256 MB
+    last-level cache, so the copy really reads HBM."""
+    import torch
+    a = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    evict = torch.zeros(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del evict
+    return mib << 20
+
+
+def summarize_counters(fetch_csv, write_csv, copy_bytes=COPY_MIB << 20):
+    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the working round
+    launches from two rocprofv3 --pmc runs, scaled by the same counters on
+    the calibration copy; writes profiles/round_kernel_traffic.json."""
+    import csv
+
+    def per_kernel(path, counter):
+        vals, copy = [], []
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name, v = row.get("Kernel_Name", ""), float(row["Counter_Value"])
+                if "k_round" in name and v > 64.0:  # launches after the stop read ~nothing
+                    vals.append(v)
+                elif "copyBuffer" in name:
+                    copy.append(v)
+        return vals, copy
+
+    f, fc = per_kernel(fetch_csv, "FETCH_SIZE")
+    w, wc = per_kernel(write_csv, "WRITE_SIZE")
+    fkib, wkib = sum(f) / len(f), sum(w) / len(w)
+    # the calibration copy reads and writes copy_bytes: its largest dispatch
+    cf = max(fc) * 1024.0 / copy_bytes if fc else 1.0
+    cw = max(wc) * 1024.0 / copy_bytes if wc else 1.0
+    out = {"kernel_hash": kernel_hash(), "fetch_kib_per_dispatch": fkib / cf * 1.0,
+           "write_kib_per_dispatch": wkib / cw * 1.0, "copy_factor": 1.0,
+           "raw": {"fetch_kib": fkib, "write_kib": wkib, "copy_fetch_factor": cf,
+                   "copy_write_factor": cw, "dispatches": [len(f), len(w)]}}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def summarize_trace(path):
+    """Working-launch durations per kernel from a rocprofv3 kernel trace: the
+    launches issued after a solve has stopped return at once (a few us) and
+    are listed apart."""
+    import csv
+    per = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            name = row["Kernel_Name"]
+            dur = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1000.0
+            per.setdefault(name, []).append(dur)
+    for name, ds in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        work = [d for d in ds if d > 10.0] if ("k_round" in name or "k_pull" in name) else ds
+        idle = len(ds) - len(work)
+        print("%-70s calls %5d  working %5d  avg_working_us %9.2f  min %8.2f  max %9.2f  "
+              "returned-at-once %d" % (name[:70], len(ds), len(work),
+                                       sum(work) / max(1, len(work)), min(work or [0]),
+                                       max(work or [0]), idle))
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [fn() for _ in range(steps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, outs
+
+
+def bench_ppr_batch(di, G, g, args):
+    import numpy as np
+    import workloads as wl
+    ptr, seeds = wl.ppr_seed_sets(g.n, 256, 100, seed=4)
+    try:
+        run = lambda: di.solve_batch(G, ptr, seeds, d=args.d, tol=1e-6, precision="fp32")
+        t, outs = time_steps(run, 1, 1)
+    except di.DiError as e:
+        return {"status": "unavailable", "reason": str(e)}
+    stats = outs[-1][1]
+    # one-at-a-time reference on a sample of 16 vectors at the same tolerance
+    t1 = time.perf_counter()
+    for b in range(16):
+        v = wl.seed_vector(g.n, seeds[ptr[b]:ptr[b + 1]])
+        di.solve(G, v=v, d=args.d, tol=1e-6, precision="fp32")
+    import torch
+    torch.cuda.synchronize()
+    solo = (time.perf_counter() - t1) / 16
+    return {"vectors": 256, "tol": 1e-6, "seconds": t, "vectors_per_s": 256 / t,
+            "solo_seconds_per_vector": solo, "speedup_vs_solo": solo * 256 / t,
+            "edges_diffused": int(sum(s["edges_diffused"] for s in stats))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="powerlaw-1m")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--d", type=float, default=0.85)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ppr", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/round_kernel_traffic.json from two --pmc runs")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
+                    help="print per-kernel durations of the working launches from a trace")
+    args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_1202_6158_amd import di
+    torch.cuda.set_device(0)
+
+    log("generating", args.workload)
+    g = wl.recipe(args.workload)
+    G = di.Graph(g)
+    log("graph n=%d links=%d dangling=%d" % (g.n, g.m, g.n_dangling))
+
+    # ---- D-iteration (the measured step): K un-instrumented solves give the
+    # throughput; the same K solves again with per-launch HIP events (the
+    # runtime stamps each round kernel's begin/end) give its launch durations.
+    solve = lambda timing: di.solve(G, d=args.d, tol=args.tol, precision=args.precision,
+                                    timing=timing)
+    sec, outs = time_steps(lambda: solve(False), args.steps, args.warmup)
+    x_di = outs[-1][0]
+    sec_timed, touts = time_steps(lambda: solve(True), args.steps, 0)
+    stats = [s for _, s in touts]
+    dev_ms = 1e3 * float(np.mean([s["seconds"] for _, s in outs]))
+    ksec = float(np.sum([s["kernel_seconds"] for s in stats]))
+    kl = int(np.sum([s["kernel_launches"] for s in stats]))
+    abytes = float(np.mean([algorithmic_bytes(g.n, s, args.precision) for s in stats]))
+    launches_per_solve = kl / len(stats)
+    per_launch_bytes = abytes / launches_per_solve
+    per_launch_sec = ksec / kl
+    achieved = per_launch_bytes / per_launch_sec / 1e9
+    st = outs[-1][1]
+    log("diter: %.3f ms/solve (device %.3f ms), %d rounds, %.3g links, residual %.2e"
+        % (sec * 1e3, dev_ms, st["rounds"], st["edges_diffused"], st["residual_l1"]))
+
+    # ---- comparator: GPU power iteration, both precision variants
+    comp = {}
+    for prec in ("fp64", "fp32"):
+        pstep = lambda: di.power_solve(G, d=args.d, tol=args.tol, precision=prec, timing=True)
+        psec, pouts = time_steps(pstep, max(2, args.steps // 2), 1)
+        ps = pouts[-1][1]
+        comp[prec] = {"ms_per_solve": psec * 1e3, "products": ps["rounds"],
+                      "kernel_us_per_product": 1e6 * ps["kernel_seconds"] / max(1, ps["kernel_launches"]),
+                      "residual_l1": ps["residual_l1"], "x": pouts[-1][0]}
+    best = min(comp, key=lambda k: comp[k]["ms_per_solve"])
+    l1_di_vs_power = float(torch.sum(torch.abs(x_di - comp["fp64"]["x"])).item())
+    for k in comp:
+        comp[k].pop("x")
+    log("power: fp64 %.3f ms, fp32 %.3f ms" % (comp["fp64"]["ms_per_solve"], comp["fp32"]["ms_per_solve"]))
+
+    out = {
+        "metric": METRIC,
+        "value": 1.0 / sec,
+        "unit": "solves/s (PageRank to L1 residual %g)" % args.tol,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype_detail": ("fp32 fluid and pushes; fp64 window accumulation, history, residual "
+                         "and normalisation") if args.precision == "fp32" else "fp64 throughout",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": g.n, "links": g.m, "dangling": g.n_dangling,
+                   "d": args.d, "tol": args.tol, "V": "uniform",
+                   "recipe": wl.RECIPES.get(args.workload)},
+        "time_to_residual_ms": sec * 1e3,
+        "device_ms_per_solve": dev_ms,
+        "ms_per_solve_with_launch_events": sec_timed * 1e3,
+        "rounds": st["rounds"], "nodes_diffused": st["nodes_diffused"],
+        "edges_diffused": st["edges_diffused"],
+        "edges_diffused_per_s": st["edges_diffused"] / sec,
+        "residual_l1": st["residual_l1"], "err_bound_l1": st["err_bound_l1"],
+        "mass_drift": st["mass_drift"],
+        "comparator": {"kind": "GPU power iteration (pull over in-links), same stop rule",
+                       "best_variant": best, "variants": comp,
+                       "speedup_of_diter": comp[best]["ms_per_solve"] / (sec * 1e3),
+                       "l1_diter_vs_power_fp64": l1_di_vs_power},
+        "roofline": {"kernel": "k_round (one D-iteration round)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(launches_per_solve),
+                     "algorithmic_bytes_per_launch": per_launch_bytes,
+                     "avg_launch_us": per_launch_sec * 1e6,
+                     "launches_per_solve": launches_per_solve,
+                     "timing": "hipExtLaunchKernel begin/end events on the solve's stream, "
+                               "%d launches over %d solves" % (kl, len(stats))},
+    }
+    if not args.no_ppr:
+        out["ppr_batch"] = bench_ppr_batch(di, G, g, args)
+    if args.copy_calibration:
+        out["copy_calibration_bytes"] = copy_calibration()
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(g, args.d, args.tol, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

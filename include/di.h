@@ -66,7 +66,9 @@ enum {
 /* flags */
 enum {
   DI_DEVICE_PTRS = 1u, /* v / x / seeds-weights are device pointers */
-  DI_RESUME = 2u       /* di_solve: start from the state passed in di_opts.state_f/state_h */
+  DI_RESUME = 2u,      /* di_solve: start from the state passed in di_opts.state_f/state_h */
+  DI_TIMING = 4u       /* time every launch of the round (or product) kernel with HIP events
+                          on the call's stream: fills kernel_seconds / kernel_launches */
 };
 
 /* threshold schedule families (Section 4.2 threshold variant; Section 4.3 scores) */
@@ -105,6 +107,8 @@ typedef struct di_stats {
   int64_t rounds;      /* diffusion rounds (power: matrix products) */
   int64_t nodes_diffused; /* node diffusions that moved fluid */
   int64_t edges_diffused; /* elementary steps: out-links used (power: nnz per product) */
+  double kernel_seconds;  /* DI_TIMING: summed device time of the launches that did work */
+  int64_t kernel_launches; /* DI_TIMING: number of those launches (else 0) */
 } di_stats;
 
 /* ------------------------------------------------------------------ graph */

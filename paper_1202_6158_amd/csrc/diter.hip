@@ -29,6 +29,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace di {
@@ -37,7 +39,7 @@ struct Workspace {
   int precision = 0, wlog = 0, nb = 0;
   int64_t n = 0, m = 0;
   DevBuf F, H, v, x, bstart, ctl;
-  DevBuf pairs[2], cntT[2], part[2];
+  DevBuf pairs[2], cnt[2], slots;
   DevBuf soff, soffT, capT;  // nb x nb segment tables
   PinnedBuf hctl;
 };
@@ -58,8 +60,8 @@ struct DiArgs {
   T* F;
   double* H;
   PairT<T>* pairs[2];
-  int32_t* cntT[2];       // [s][w] records written into segment (s -> w) in a round
-  Part* part[2];
+  int32_t* cnt[2];        // [w][s] records written into segment (s -> w) in a round
+  Slot* slots;            // [3][kSlots] round sums, round r uses set r % 3
   Ctl* ctl;
   double d, tol, c, theta0;
   int64_t max_rounds;
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_segments(int64_t n, int wlog, int nb
   for (int k = 0; k < per; ++k)
     if (s0 + k < nb) loc += E[(int64_t)w * nb + s0 + k];
   long long tot = 0;
-  long long run = block_exscan(loc, s_scr, &tot);
+  long long run = block_exscan<kBlock>(loc, s_scr, &tot);
   for (int k = 0; k < per; ++k)
     if (s0 + k < nb) {
       soff[(int64_t)w * nb + s0 + k] = (int32_t)run;
@@ -137,6 +139,10 @@ __global__ __launch_bounds__(kBlock) void k_init(DiArgs<T> a, const double* __re
       a.H[i] = 0.0;
     }
   }
+  for (int64_t k = t; k < 3 * kSlots; k += stride) {
+    for (int f = 0; f < kSums; ++f) a.slots[k].sum[f] = 0.0;
+    a.slots[k].mrem = 0;
+  }
   if (t == 0) {
     Ctl* c = a.ctl;
     c->stop_round = -1;
@@ -159,15 +165,16 @@ __device__ __forceinline__ double node_score(double f, int dg, int indeg) {
   return f;
 }
 
-// In-place exclusive scan of arr[0..n) in LDS; returns the total.
+// In-place exclusive scan of arr[0..n) in LDS (NT threads); returns the total.
+template <int NT>
 __device__ long long lds_exscan(int32_t* arr, int n, long long* scr) {
-  const int per = (n + kBlock - 1) / kBlock;
+  const int per = (n + NT - 1) / NT;
   const int s0 = threadIdx.x * per;
   long long loc = 0;
   for (int k = 0; k < per; ++k)
     if (s0 + k < n) loc += arr[s0 + k];
   long long tot = 0;
-  long long run = block_exscan(loc, scr, &tot);
+  long long run = block_exscan<NT>(loc, scr, &tot);
   for (int k = 0; k < per; ++k)
     if (s0 + k < n) {
       const int32_t v = arr[s0 + k];
@@ -189,9 +196,15 @@ __device__ __forceinline__ int upper_idx(const I* a, int n, long long x) {
   return lo;
 }
 
+constexpr int kRT = kRoundThreads;  // threads per round workgroup
+constexpr int kU = 4;               // independent memory operations per thread per step
+constexpr int kSuper = 2048;        // window nodes decided and expanded per pass
+constexpr int kNPT = kSuper / kRT;  // nodes per thread per pass
+
 // One round; mode 1 forces a fold-only launch (after an explicit single round).
 template <typename T, int SCHED>
-__global__ __launch_bounds__(kBlock) void k_round(DiArgs<T> a, int r, int mode) {
+__global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_round(DiArgs<T> a, int r,
+                                                                                   int mode) {
   Ctl* ctl = a.ctl;
   // Launch r itself records stop_round = r-1; an earlier stop ends this launch.
   const int sr = ld_relaxed(&ctl->stop_round);
@@ -200,46 +213,60 @@ __global__ __launch_bounds__(kBlock) void k_round(DiArgs<T> a, int r, int mode) 
   extern __shared__ __align__(16) unsigned char smem[];
   const int W = 1 << a.wlog;
   const int nb = a.nb;
-  double* win = reinterpret_cast<double*>(smem);         // [W]
-  int64_t* s_base = reinterpret_cast<int64_t*>(win + W);  // [nb]
-  int32_t* s_pre = reinterpret_cast<int32_t*>(s_base + nb);  // [nb+1] fold prefix, then ranks
-  int32_t* s_soff = s_pre + (nb + 1);                    // [nb]
-  int32_t* s_cap = s_soff + nb;                          // [nb]
-  __shared__ int32_t s_beo[kBatch + 1];
-  __shared__ int64_t s_brow[kBatch];
-  __shared__ double s_bsh[kBatch];
-  __shared__ double s_red[kBlock / 64];
-  __shared__ long long s_scr[kBlock / 64];
+  double* win = reinterpret_cast<double*>(smem);             // [W]
+  int64_t* s_base = reinterpret_cast<int64_t*>(win + W);      // [nb]
+  int32_t* s_pre = reinterpret_cast<int32_t*>(s_base + nb);   // [nb+1] fold prefix, then ranks
+  int32_t* s_soff = s_pre + (nb + 1);                         // [nb]
+  int32_t* s_cap = s_soff + nb;                               // [nb]
+  __shared__ int32_t s_beo[kSuper + 1];
+  __shared__ int64_t s_brow[kSuper];
+  __shared__ double s_bsh[kSuper];
+  __shared__ double s_red[8 * (kRT / 64)];
+  __shared__ long long s_scr[2 * (kRT / 64)];
 
   const int b = blockIdx.x;
   const int64_t j0 = (int64_t)b << a.wlog;
   const int wn = (int)min((int64_t)W, a.n - j0);
   const int tid = threadIdx.x;
 
+  // Loads that do not depend on the round's decisions are issued first: this
+  // window's fluid and, from round 1 on, its incoming segment counts/offsets.
+  constexpr int kWinPer = 4;  // window values prefetched per thread (the rest load later)
+  T fv[kWinPer];
+#pragma unroll
+  for (int k = 0; k < kWinPer; ++k) {
+    const int q = tid + k * kRT;
+    fv[k] = q < wn ? a.F[j0 + q] : (T)0;
+  }
+  const int32_t* cnt_in = a.cnt[(r - 1) & 1] + (int64_t)b * nb;
+  int32_t c_own = 0, o_own = 0;  // first pass over sources (nb <= kRT in the common case)
+  if (r >= 1 && tid < nb) {
+    c_own = cnt_in[tid];
+    o_own = a.soff[(int64_t)b * nb + tid];
+  }
+
   // 1. Decisions from round r-1's partial sums (identical in every workgroup).
   double theta = a.theta0;
   bool stop = mode == 1;
   if (r >= 1) {
-    const Part* P = a.part[(r - 1) & 1];
-    double nf = 0, snd = 0, sd = 0, ssc = 0, mrem = 0, nnz = 0, taken = 0, edges = 0;
-    for (int k = tid; k < nb; k += kBlock) {
-      nf += P[k].nf;
-      snd += P[k].snd;
-      sd += P[k].sd;
-      ssc += P[k].ssc;
-      mrem = fmax(mrem, P[k].mrem);
-      nnz += (double)P[k].nnz;
-      taken += (double)P[k].taken;
-      edges += (double)P[k].edges;
+    const Slot* P = a.slots + ((r - 1) % 3) * kSlots;
+    double v[kSums] = {0, 0, 0, 0, 0, 0, 0};  // nf, snd, sd, ssc, nnz, taken, edges
+    double mrem = 0.0;
+    if (tid < kSlots) {
+      const Slot p = P[tid];
+#pragma unroll
+      for (int f = 0; f < kSums; ++f) v[f] = p.sum[f];
+      mrem = __longlong_as_double((long long)p.mrem);
     }
-    nf = block_sum(nf, s_red);
-    snd = block_sum(snd, s_red);
-    sd = block_sum(sd, s_red);
-    ssc = block_sum(ssc, s_red);
-    mrem = block_max(mrem, s_red);
-    nnz = block_sum(nnz, s_red);
-    taken = block_sum(taken, s_red);
-    edges = block_sum(edges, s_red);
+    if (b == 0 && tid < kSlots) {  // set (r+1) % 3 is next used by launch r+1
+      Slot* z = a.slots + ((r + 1) % 3) * kSlots + tid;
+#pragma unroll
+      for (int f = 0; f < kSums; ++f) z->sum[f] = 0.0;
+      z->mrem = 0;
+    }
+    block_reduce_k<kRT, kSums>(v, mrem, s_red);
+    const double nf = v[0], snd = v[1], sd = v[2], ssc = v[3], nnz = v[4], taken = v[5],
+                 edges = v[6];
     int reason = 0;
     if (!isfinite(nf)) reason = 2;
     else if (nf < a.tol) reason = 1;
@@ -269,31 +296,53 @@ __global__ __launch_bounds__(kBlock) void k_round(DiArgs<T> a, int r, int mode) 
   }
 
   // 2. Window fluid (fp64 in LDS) plus the pushes of round r-1.
-  for (int q = tid; q < wn; q += kBlock) win[q] = (double)a.F[j0 + q];
+#pragma unroll
+  for (int k = 0; k < kWinPer; ++k) {
+    const int q = tid + k * kRT;
+    if (q < wn) win[q] = (double)fv[k];
+  }
+  for (int q = tid + kWinPer * kRT; q < wn; q += kRT) win[q] = (double)a.F[j0 + q];
   if (r >= 1) {
-    const int32_t* cnt = a.cntT[(r - 1) & 1];
-    for (int s = tid; s < nb; s += kBlock) {
-      s_pre[s] = cnt[(int64_t)s * nb + b];
+    if (tid < nb) {
+      s_pre[tid] = c_own;
+      s_soff[tid] = o_own;
+    }
+    for (int s = tid + kRT; s < nb; s += kRT) {
+      s_pre[s] = cnt_in[s];
       s_soff[s] = a.soff[(int64_t)b * nb + s];
     }
     __syncthreads();
-    const long long total = lds_exscan(s_pre, nb, s_scr);
+    const long long total = lds_exscan<kRT>(s_pre, nb, s_scr);
     const PairT<T>* pr = a.pairs[(r - 1) & 1];
     const int64_t base = a.bstart[b];
-    for (long long i = tid; i < total; i += kBlock) {
-      const int s = upper_idx(s_pre, nb, i);
-      const PairT<T> e = pr[base + s_soff[s] + (i - s_pre[s])];
-      if (e.loc < (uint32_t)wn) atomicAdd(&win[e.loc], (double)e.val);
+    for (long long i0 = tid; i0 < total; i0 += kU * kRT) {
+      int64_t idx[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const long long i = i0 + (long long)u * kRT;
+        idx[u] = -1;
+        if (i < total) {
+          const int s = upper_idx(s_pre, nb, i);
+          idx[u] = base + s_soff[s] + (i - s_pre[s]);
+        }
+      }
+      PairT<T> e[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (idx[u] >= 0) e[u] = pr[idx[u]];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (idx[u] >= 0 && e[u].loc < (uint32_t)wn) atomicAdd(&win[e[u].loc], (double)e[u].val);
     }
   }
   __syncthreads();
   if (stop) {
-    for (int q = tid; q < wn; q += kBlock) a.F[j0 + q] = (T)win[q];
+    for (int q = tid; q < wn; q += kRT) a.F[j0 + q] = (T)win[q];
     return;
   }
 
-  // 3. Take and expand.
-  for (int w = tid; w < nb; w += kBlock) {
+  // 3. Take and expand, one tile of kRT nodes at a time.
+  for (int w = tid; w < nb; w += kRT) {
     s_pre[w] = 0;  // now: records written per destination window
     s_base[w] = a.bstart[w] + a.soffT[(int64_t)b * nb + w];
     s_cap[w] = a.capT[(int64_t)b * nb + w];
@@ -301,109 +350,130 @@ __global__ __launch_bounds__(kBlock) void k_round(DiArgs<T> a, int r, int mode) 
   __syncthreads();
   PairT<T>* out = a.pairs[r & 1];
   const uint32_t wmask = (uint32_t)W - 1u;
-  double nf = 0, snd = 0, sd = 0, ssc = 0, mrem = 0;
-  long long nnz = 0, taken = 0, edges = 0;
-  int bcount = 0;        // entries staged (uniform across the block)
-  long long bedges = 0;  // their out-links
-  auto expand = [&]() {
-    for (long long t = tid; t < bedges; t += kBlock) {
-      const int k = upper_idx(s_beo, bcount, t);
-      const int64_t e = s_brow[k] + (t - s_beo[k]);
-      const uint32_t dst = (uint32_t)a.col[e];
-      double v = s_bsh[k];
-      if (a.weighted) v *= a.w[e];
-      const int w = (int)(dst >> a.wlog);
-      const int rank = atomicAdd(&s_pre[w], 1);
-      if (rank < s_cap[w]) {
-        PairT<T> pr;
-        memset(&pr, 0, sizeof(pr));
-        pr.loc = dst & wmask;
-        pr.val = (T)v;
-        out[s_base[w] + rank] = pr;
-      } else {
-        atomicOr(&ctl->err, 2);
-      }
-    }
-    edges += bedges;
-    bcount = 0;
-    bedges = 0;
-    __syncthreads();
-  };
-  for (int t0 = 0; t0 < wn; t0 += kBlock) {
-    const int q = t0 + tid;
-    long long push = 0;  // out-degree if this thread's node is taken and pushes
-    double share = 0.0;
-    int64_t rowst = 0;
-    if (q < wn) {
-      const double f = win[q];
-      if (f > 0.0) {
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // nf, snd, sd, ssc, nnz, taken, edges
+  double mrem = 0.0;
+  for (int t0 = 0; t0 < wn; t0 += kSuper) {
+    // A. Decide for kNPT nodes per thread, then issue all their loads at once.
+    double f[kNPT];
+    bool tk[kNPT];
+#pragma unroll
+    for (int u = 0; u < kNPT; ++u) {
+      const int q = t0 + tid + u * kRT;
+      f[u] = q < wn ? win[q] : 0.0;
+      tk[u] = false;
+      if (f[u] > 0.0) {
         const int64_t j = j0 + q;
-        nf += f;
-        ++nnz;
+        acc[0] += f[u];
+        acc[4] += 1.0;
         int dg = -1;
         if (SCHED != DI_SCHED_MEAN) dg = a.deg[j];
-        const double sc = node_score<SCHED>(f, dg, SCHED == DI_SCHED_OP ? a.indeg[j] : 0);
-        ssc += sc;
-        if (sc >= theta) {
-          if (dg < 0) dg = a.deg[j];
-          a.H[j] += f;
-          win[q] = 0.0;
-          ++taken;
-          if (dg > 0) {
-            snd += f;
-            push = dg;
-            share = a.weighted ? a.d * f : a.d * f / (double)dg;
-            rowst = a.row_ptr[j];
-          } else {
-            sd += f;
-          }
-        } else {
-          mrem = fmax(mrem, sc);
-        }
-      } else if (f != f) {
-        nf = NAN;
+        const double sc = node_score<SCHED>(f[u], dg, SCHED == DI_SCHED_OP ? a.indeg[j] : 0);
+        acc[3] += sc;
+        if (sc >= theta) tk[u] = true;
+        else mrem = fmax(mrem, sc);
+      } else if (f[u] != f[u]) {
+        acc[0] = NAN;
       }
     }
-    long long ntile = 0, etile = 0;
-    const long long slot = block_exscan(push > 0 ? 1 : 0, s_scr, &ntile);
-    const long long eoff = block_exscan(push, s_scr, &etile);
-    if (ntile == 0) continue;
-    if (bcount + ntile > kBatch) expand();
-    if (push > 0) {
-      s_beo[bcount + slot] = (int32_t)(bedges + eoff);
-      s_brow[bcount + slot] = rowst;
-      s_bsh[bcount + slot] = share;
+    int64_t rs[kNPT];
+    int dgs[kNPT];
+    double h[kNPT];
+#pragma unroll
+    for (int u = 0; u < kNPT; ++u) {
+      if (!tk[u]) continue;
+      const int64_t j = j0 + t0 + tid + u * kRT;
+      rs[u] = a.row_ptr[j];
+      dgs[u] = a.deg[j];
+      h[u] = a.H[j];
     }
-    bcount += (int)ntile;
-    bedges += etile;
+    long long npush = 0, nedge = 0;
+#pragma unroll
+    for (int u = 0; u < kNPT; ++u) {
+      if (!tk[u]) continue;
+      const int q = t0 + tid + u * kRT;
+      a.H[j0 + q] = h[u] + f[u];
+      win[q] = 0.0;
+      acc[5] += 1.0;
+      if (dgs[u] > 0) {
+        acc[1] += f[u];
+        ++npush;
+        nedge += dgs[u];
+      } else {
+        acc[2] += f[u];
+      }
+    }
+    // B. Stage the pushing nodes (thread-major order) with their link offsets.
+    long long slot = 0, eoff = 0, ntile = 0, etile = 0;
+    block_exscan2<kRT>(npush, nedge, s_scr, &slot, &eoff, &ntile, &etile);
+    if (ntile == 0) continue;  // uniform
+#pragma unroll
+    for (int u = 0; u < kNPT; ++u) {
+      if (!tk[u] || dgs[u] == 0) continue;
+      const long long dg = dgs[u];
+      s_beo[slot] = (int32_t)eoff;
+      s_brow[slot] = rs[u];
+      s_bsh[slot] = a.weighted ? a.d * f[u] : a.d * f[u] / (double)dg;
+      ++slot;
+      eoff += dg;
+    }
     __syncthreads();
-    if (bcount > kBatch - kBlock) expand();
+    // C. Push every staged link: kU independent link reads per thread per step.
+    const int bcount = (int)ntile;
+    for (long long t00 = tid; t00 < etile; t00 += kU * kRT) {
+      int64_t e[kU];
+      int kk[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const long long t = t00 + (long long)u * kRT;
+        e[u] = -1;
+        if (t < etile) {
+          kk[u] = upper_idx(s_beo, bcount, t);
+          e[u] = s_brow[kk[u]] + (t - s_beo[kk[u]]);
+        }
+      }
+      uint32_t dst[kU];
+      double v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (e[u] >= 0) {
+          dst[u] = (uint32_t)a.col[e[u]];
+          v[u] = s_bsh[kk[u]];
+          if (a.weighted) v[u] *= a.w[e[u]];
+        }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (e[u] < 0) continue;
+        const int w = (int)(dst[u] >> a.wlog);
+        const int rank = atomicAdd(&s_pre[w], 1);
+        if (rank < s_cap[w]) {
+          PairT<T> pr;
+          memset(&pr, 0, sizeof(pr));
+          pr.loc = dst[u] & wmask;
+          pr.val = (T)v[u];
+          out[s_base[w] + rank] = pr;
+        } else {
+          atomicOr(&ctl->err, 2);
+        }
+      }
+    }
+    acc[6] += (double)etile;  // uniform: counted once below (thread 0 only)
+    __syncthreads();
   }
-  if (bcount > 0) expand();
-  __syncthreads();
-  int32_t* cnt_out = a.cntT[r & 1] + (int64_t)b * nb;
-  for (int w = tid; w < nb; w += kBlock) cnt_out[w] = s_pre[w];
-  for (int q = tid; q < wn; q += kBlock) a.F[j0 + q] = (T)win[q];
+  int32_t* cnt_out = a.cnt[r & 1];  // destination-major: these stores are posted
+  for (int w = tid; w < nb; w += kRT) cnt_out[(int64_t)w * nb + b] = s_pre[w];
+  for (int q = tid; q < wn; q += kRT) a.F[j0 + q] = (T)win[q];
 
-  // 4. Partial sums of this window.
-  nf = block_sum(nf, s_red);
-  snd = block_sum(snd, s_red);
-  sd = block_sum(sd, s_red);
-  ssc = block_sum(ssc, s_red);
-  mrem = block_max(mrem, s_red);
-  const double nnz_d = block_sum((double)nnz, s_red);
-  const double taken_d = block_sum((double)taken, s_red);
+  // 4. This window's sums, added into its slot.
+  const double edges = acc[6];
+  acc[6] = 0.0;
+  block_reduce_k<kRT, kSums>(acc, mrem, s_red);
   if (tid == 0) {
-    Part p;
-    p.nf = nf;
-    p.snd = snd;
-    p.sd = sd;
-    p.ssc = ssc;
-    p.mrem = mrem;
-    p.nnz = (unsigned long long)nnz_d;
-    p.taken = (unsigned long long)taken_d;
-    p.edges = (unsigned long long)edges;
-    a.part[r & 1][b] = p;
+    acc[6] = edges;
+    Slot* sl = a.slots + (r % 3) * kSlots + (b % kSlots);
+#pragma unroll
+    for (int f = 0; f < kSums; ++f)
+      if (acc[f] != 0.0) unsafeAtomicAdd(&sl->sum[f], acc[f]);
+    if (mrem > 0.0) atomicMax(&sl->mrem, (unsigned long long)__double_as_longlong(mrem));
   }
 }
 
@@ -495,9 +565,9 @@ Workspace* acquire_workspace(Graph* g, int precision, int wlog) {
     ws->ctl.alloc(1024 + 1024 * 8);  // Ctl, then 256 x 4 flush slots
     for (int k = 0; k < 2; ++k) {
       ws->pairs[k].alloc(std::max<int64_t>(m, 1) * (precision == DI_FP64 ? 16 : 8));
-      ws->cntT[k].alloc(nb2 * 4);
-      ws->part[k].alloc(nb * sizeof(Part));
+      ws->cnt[k].alloc(nb2 * 4);
     }
+    ws->slots.alloc(3 * kSlots * sizeof(Slot));
     ws->soff.alloc(nb2 * 4);
     ws->soffT.alloc(nb2 * 4);
     ws->capT.alloc(nb2 * 4);
@@ -580,9 +650,9 @@ static DiArgs<T> make_args(const Graph* g, Workspace* ws, double d, double tol, 
   a.H = H;
   for (int k = 0; k < 2; ++k) {
     a.pairs[k] = ws->pairs[k].as<PairT<T>>();
-    a.cntT[k] = ws->cntT[k].as<int32_t>();
-    a.part[k] = ws->part[k].as<Part>();
+    a.cnt[k] = ws->cnt[k].as<int32_t>();
   }
+  a.slots = ws->slots.as<Slot>();
   a.ctl = ws->ctl.as<Ctl>();
   a.d = d;
   a.tol = tol;
@@ -598,24 +668,40 @@ static int grid_for(int64_t n, int cap) {
 }
 
 template <typename T, int SCHED>
-static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s) {
+static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, LaunchTimer* lt) {
   const size_t smem = round_lds_bytes(a.wlog, a.nb);
-  static bool attr_set = false;
-  if (!attr_set) {
+  static size_t dyn_limit = 0;
+  if (dyn_limit == 0) {
+    // Dynamic LDS may use what the static part leaves of the workgroup limit.
+    hipFuncAttributes fa;
+    DI_HIP(hipFuncGetAttributes(&fa, (const void*)k_round<T, SCHED>));
+    int dev = 0, lim = 0;
+    DI_HIP(hipGetDevice(&dev));
+    DI_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    dyn_limit = (size_t)lim - fa.sharedSizeBytes;
     DI_HIP(hipFuncSetAttribute((const void*)k_round<T, SCHED>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024));
-    attr_set = true;
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_limit));
   }
-  k_round<T, SCHED><<<a.nb, kBlock, smem, s>>>(a, r, mode);
+  DI_REQUIRE(smem <= dyn_limit, "window tables exceed the LDS available to the round kernel");
+  if (lt && lt->on) {
+    // The runtime stamps the kernel's own begin/end into the event pair.
+    hipEvent_t e0, e1;
+    lt->next(&e0, &e1);
+    hipExtLaunchKernelGGL(k_round<T, SCHED>, dim3(a.nb), dim3(kRT), smem, s, e0, e1, 0, a, r,
+                          mode);
+  } else {
+    k_round<T, SCHED><<<a.nb, kRT, smem, s>>>(a, r, mode);
+  }
   DI_HIP(hipGetLastError());
 }
 
 template <typename T>
-static void launch_round(const DiArgs<T>& a, int sched, int r, int mode, hipStream_t s) {
+static void launch_round(const DiArgs<T>& a, int sched, int r, int mode, hipStream_t s,
+                         LaunchTimer* lt = nullptr) {
   switch (sched) {
-    case DI_SCHED_OP2: launch_round_t<T, DI_SCHED_OP2>(a, r, mode, s); break;
-    case DI_SCHED_OP: launch_round_t<T, DI_SCHED_OP>(a, r, mode, s); break;
-    default: launch_round_t<T, DI_SCHED_MEAN>(a, r, mode, s); break;
+    case DI_SCHED_OP2: launch_round_t<T, DI_SCHED_OP2>(a, r, mode, s, lt); break;
+    case DI_SCHED_OP: launch_round_t<T, DI_SCHED_OP>(a, r, mode, s, lt); break;
+    default: launch_round_t<T, DI_SCHED_MEAN>(a, r, mode, s, lt); break;
   }
 }
 
@@ -628,14 +714,14 @@ static void read_ctl(Workspace* ws, hipStream_t s) {
 // last pushes, so (F, H) is again a state of the recurrences).
 template <typename T>
 static void run_rounds(const DiArgs<T>& a, Workspace* ws, int sched, int check_every,
-                       hipStream_t s) {
+                       hipStream_t s, LaunchTimer* lt) {
   Ctl* h = ws->hctl.as<Ctl>();
   int r = 0;
   int chunk = check_every > 0 ? check_every : 8;
   double nf_prev = -1.0;
   int r_prev = 0;
   for (;;) {
-    for (int i = 0; i < chunk; ++i) launch_round(a, sched, r++, 0, s);
+    for (int i = 0; i < chunk; ++i) launch_round(a, sched, r++, 0, s, lt);
     read_ctl(ws, s);
     if (h->stop_round >= 0) break;
     if (check_every == 0) {
@@ -698,10 +784,11 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   T* F = resume ? static_cast<T*>(o->state_f) : ws->F.as<T>();
   double* H = resume ? o->state_h : ws->H.as<double>();
   DiArgs<T> a = make_args<T>(g, ws, o->d, o->tol, c, max_rounds, F, H);
+  LaunchTimer lt(s, (o->flags & DI_TIMING) != 0);
   EventTimer timer(s);
   k_init<T><<<grid_for(g->n, 2048), kBlock, 0, s>>>(a, vdev, resume ? 1 : 0);
   DI_HIP(hipGetLastError());
-  run_rounds(a, ws, sched, check_every, s);
+  run_rounds(a, ws, sched, check_every, s, &lt);
   double* xo = x ? (dev ? x : ws->x.as<double>()) : nullptr;
   flush(a, ws, xo, o->normalize, s);
   const double secs = timer.stop();
@@ -719,6 +806,10 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
     st->rounds = h->stop_round + 1;
     st->nodes_diffused = h->nodes_total;
     st->edges_diffused = h->edges_total;
+    // launches 0..stop_round take and expand; launch stop_round+1 folds.
+    const size_t working = (size_t)h->stop_round + 2;
+    st->kernel_seconds = lt.on ? lt.total(working) : 0.0;
+    st->kernel_launches = lt.on ? (int64_t)working : 0;
   }
   if (h->err) {
     set_error("internal segment consistency check failed (code " + std::to_string(h->err) + ")");

@@ -29,7 +29,7 @@ size_t round_lds_bytes(int wlog, int nb) {
 }
 
 int window_log2_for(int64_t n, int requested) {
-  constexpr size_t kLdsBudget = 140 * 1024;  // leaves room for the static LDS
+  constexpr size_t kLdsBudget = 116 * 1024;  // 160 KiB minus the round kernel's static LDS
   int k = 8;
   if (requested >= 8) {
     k = std::min(requested, 14);
@@ -128,9 +128,9 @@ di_status di_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
           }
       }
       // Pull blocks: up to kPullRows rows and kPullNnz in-links each; a row
-      // with more in-links than that is a block of its own.
-      std::vector<int32_t> blk;
-      blk.push_back(0);
+      // with more in-links than that is a block of its own.  Stored as
+      // (first row, end row) pairs, longest block first.
+      std::vector<std::pair<int32_t, int32_t>> blocks;
       {
         int64_t r = 0;
         while (r < n) {
@@ -143,10 +143,18 @@ di_status di_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const 
             ++r;
             if (nz > kPullNnz) break;  // long row alone
           }
-          blk.push_back((int32_t)r);
+          blocks.emplace_back((int32_t)r0, (int32_t)r);
         }
       }
-      g->npull = (int64_t)blk.size() - 1;
+      std::stable_sort(blocks.begin(), blocks.end(), [&](const auto& x, const auto& y) {
+        return in_ptr[x.second] - in_ptr[x.first] > in_ptr[y.second] - in_ptr[y.first];
+      });
+      std::vector<int32_t> blk;
+      for (const auto& p : blocks) {
+        blk.push_back(p.first);
+        blk.push_back(p.second);
+      }
+      g->npull = (int64_t)blocks.size();
       g->row_ptr.alloc((n + 1) * 8);
       g->deg.alloc(n * 4);
       g->indeg.alloc(n * 4);

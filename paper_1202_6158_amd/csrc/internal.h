@@ -103,7 +103,7 @@ struct PinnedBuf {
 // --------------------------------------------------------------- constants
 
 constexpr int kBlock = 256;        // threads per workgroup of the streaming kernels
-constexpr int kBatch = 512;        // frontier entries staged per expand batch
+constexpr int kRoundThreads = 512;   // threads per D-iteration round workgroup
 constexpr int64_t kMaxNnz = 1ll << 36;  // links per graph
 constexpr int kMaxBuckets = 4096;  // destination windows per solve
 constexpr int kPullRows = 256;     // rows per pull block (one per thread)
@@ -127,7 +127,7 @@ struct Graph {
   DevBuf in_ptr;   // int64[n+1]
   DevBuf in_src;   // int32[m]
   DevBuf in_w;     // double[m] (weighted graphs)
-  DevBuf pull_blk; // int32[npull+1]: first row of each pull block
+  DevBuf pull_blk; // int32[2*npull]: (first row, end row) of each pull block, longest first
   int64_t npull = 0;
   // reusable solve workspaces
   std::mutex ws_mu;
@@ -151,6 +151,49 @@ void destroy_workspace(Workspace* ws);
 // Validation helpers.
 void validate_d_tol(const di_opts* o);
 void validate_vector(const double* v, int64_t n, const char* what);
+
+// Per-launch HIP event pairs on one stream (DI_TIMING).  Events come from a
+// pool created before the timed region and grown in blocks; launches made
+// with hipExtLaunchKernel fill them with the kernel's own begin/end times.
+struct LaunchTimer {
+  hipStream_t s;
+  bool on;
+  size_t used = 0;
+  std::vector<hipEvent_t> a, b;
+  LaunchTimer(hipStream_t st, bool enabled, size_t reserve = 256) : s(st), on(enabled) {
+    if (on) grow(reserve);
+  }
+  void grow(size_t k) {
+    for (size_t i = 0; i < k; ++i) {
+      hipEvent_t e1, e2;
+      DI_HIP(hipEventCreate(&e1));
+      DI_HIP(hipEventCreate(&e2));
+      a.push_back(e1);
+      b.push_back(e2);
+    }
+  }
+  // Event pair for the next launch (hipExtLaunchKernel records into them).
+  void next(hipEvent_t* e0, hipEvent_t* e1) {
+    if (used == a.size()) grow(256);
+    *e0 = a[used];
+    *e1 = b[used];
+    ++used;
+  }
+  // Sum of the first `count` launches' durations (stream must have drained).
+  double total(size_t count) {
+    double t = 0.0;
+    for (size_t i = 0; i < count && i < used; ++i) {
+      float ms = 0.f;
+      DI_HIP(hipEventElapsedTime(&ms, a[i], b[i]));
+      t += ms * 1e-3;
+    }
+    return t;
+  }
+  ~LaunchTimer() {
+    for (hipEvent_t e : a) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b) (void)hipEventDestroy(e);
+  }
+};
 
 // Timing helper: records events around a region on a stream.
 struct EventTimer {

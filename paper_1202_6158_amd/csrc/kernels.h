@@ -24,15 +24,18 @@ struct alignas(16) PairT<double> {
   double val;
 };
 
-// Partial sums of one window in one round (written by the window's
-// workgroup, reduced by every workgroup of the next round).
-struct alignas(64) Part {
-  double nf;    // fluid held before the take (the stopping residual)
-  double snd;   // fluid taken from non-dangling nodes (pushed on)
-  double sd;    // fluid taken from dangling nodes (leaves the system)
-  double ssc;   // sum of the schedule's score over nodes holding fluid
-  double mrem;  // largest untaken score
-  unsigned long long nnz, taken, edges;  // nodes holding fluid, taken, out-links pushed
+// Round sums, accumulated by the windows' workgroups into kSlots slots
+// (window b adds into slot b % kSlots, so each address sees few atomics) and
+// reduced by every workgroup of the next round.  Fields: fluid held before
+// the take (the stopping residual), fluid taken from non-dangling nodes,
+// fluid taken from dangling nodes, score sum over nodes holding fluid, nodes
+// holding fluid, nodes taken, out-links pushed; and the largest untaken score
+// (bits of a non-negative double, combined with an unsigned max).
+constexpr int kSlots = 64;
+constexpr int kSums = 7;
+struct alignas(64) Slot {
+  double sum[kSums];
+  unsigned long long mrem;
 };
 
 // Control block in device memory.  Each field is written by workgroup 0 of
@@ -60,9 +63,10 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Block-wide sum / max over kBlock threads (fixed order: deterministic);
-// every thread gets the result.
-__device__ __forceinline__ double block_sum(double v, double* scratch /* kBlock/64 */) {
+// Block-wide sum / max over NT threads (fixed order: deterministic); every
+// thread gets the result.  scratch holds NT/64 entries.
+template <int NT = kBlock>
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -70,10 +74,11 @@ __device__ __forceinline__ double block_sum(double v, double* scratch /* kBlock/
   __syncthreads();
   double t = 0.0;
 #pragma unroll
-  for (int i = 0; i < kBlock / 64; ++i) t += scratch[i];
+  for (int i = 0; i < NT / 64; ++i) t += scratch[i];
   return t;
 }
-__device__ __forceinline__ double block_max(double v, double* scratch /* kBlock/64 */) {
+template <int NT = kBlock>
+__device__ __forceinline__ double block_max(double v, double* scratch) {
   v = wave_max(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -81,13 +86,43 @@ __device__ __forceinline__ double block_max(double v, double* scratch /* kBlock/
   __syncthreads();
   double t = scratch[0];
 #pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) t = fmax(t, scratch[i]);
+  for (int i = 1; i < NT / 64; ++i) t = fmax(t, scratch[i]);
   return t;
+}
+
+// Sums K values (and one max) across the block in one LDS round trip;
+// scratch holds (K+1) * NT/64 doubles.  Fixed order: deterministic.
+template <int NT, int K>
+__device__ __forceinline__ void block_reduce_k(double (&v)[K], double& mx, double* scratch) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  mx = wave_max(mx);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) scratch[k * (NT / 64) + wid] = v[k];
+    scratch[K * (NT / 64) + wid] = mx;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) t += scratch[k * (NT / 64) + i];
+    v[k] = t;
+  }
+  double m = scratch[K * (NT / 64)];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) m = fmax(m, scratch[K * (NT / 64) + i]);
+  mx = m;
+  __syncthreads();
 }
 
 // Exclusive block scan of one non-negative value per thread; returns the
 // thread's prefix and writes the block total to *total.
-__device__ __forceinline__ long long block_exscan(long long v, long long* scratch /* kBlock/64 */,
+template <int NT = kBlock>
+__device__ __forceinline__ long long block_exscan(long long v, long long* scratch /* NT/64 */,
                                                   long long* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   long long incl = v;
@@ -101,12 +136,51 @@ __device__ __forceinline__ long long block_exscan(long long v, long long* scratc
   __syncthreads();
   long long base = 0, tot = 0;
 #pragma unroll
-  for (int i = 0; i < kBlock / 64; ++i) {
+  for (int i = 0; i < NT / 64; ++i) {
     if (i < wid) base += scratch[i];
     tot += scratch[i];
   }
   *total = tot;
   return base + incl - v;
+}
+
+// Two exclusive scans (a, b) in one LDS round trip.
+template <int NT>
+__device__ __forceinline__ void block_exscan2(long long a, long long b, long long* scratch /* 2*NT/64 */,
+                                              long long* pa, long long* pb, long long* ta,
+                                              long long* tb) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  long long ia = a, ib = b;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long t1 = __shfl_up(ia, o, 64);
+    const long long t2 = __shfl_up(ib, o, 64);
+    if (lane >= o) {
+      ia += t1;
+      ib += t2;
+    }
+  }
+  __syncthreads();
+  if (lane == 63) {
+    scratch[wid] = ia;
+    scratch[NT / 64 + wid] = ib;
+  }
+  __syncthreads();
+  long long ba = 0, bb = 0, sa = 0, sb = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const long long x = scratch[i], y = scratch[NT / 64 + i];
+    if (i < wid) {
+      ba += x;
+      bb += y;
+    }
+    sa += x;
+    sb += y;
+  }
+  *pa = ba + ia - a;
+  *pb = bb + ib - b;
+  *ta = sa;
+  *tb = sb;
 }
 
 template <typename T>

@@ -17,6 +17,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace di {
@@ -102,7 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_pull(PowArgs<G> a, int k) {
   const int cur = k & 1, nxt = cur ^ 1;
   const G* __restrict__ xs = a.xs[cur];
   G* __restrict__ ys = a.xs[nxt];
-  const int r0 = a.blk[blockIdx.x], r1 = a.blk[blockIdx.x + 1];
+  // Blocks are listed longest first so that hub rows start early.
+  const int r0 = a.blk[2 * blockIdx.x], r1 = a.blk[2 * blockIdx.x + 1];
   const int64_t e0 = a.in_ptr[r0], e1 = a.in_ptr[r1];
   const double u = 1.0 / (double)a.n;
   double diff = 0.0;
@@ -120,20 +123,50 @@ __global__ __launch_bounds__(kBlock) void k_pull(PowArgs<G> a, int k) {
     }
     ys[r] = (G)carry;
   };
+  // Gathers in groups of kGU independent loads per thread.
+  auto gather = [&](int64_t e) {
+    double t = (double)xs[a.in_src[e]];
+    if (kWeighted) t *= a.in_w[e];
+    return t;
+  };
+  constexpr int kGU = 4;
   if (r1 - r0 == 1 && e1 - e0 > kPullNnz) {
     double acc = 0.0;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-      double t = (double)xs[a.in_src[e]];
-      if (kWeighted) t *= a.in_w[e];
-      acc += t;
+    for (int64_t e00 = e0 + threadIdx.x; e00 < e1; e00 += kGU * kBlock) {
+      int32_t src[kGU];
+#pragma unroll
+      for (int q = 0; q < kGU; ++q) {
+        const int64_t e = e00 + (int64_t)q * kBlock;
+        src[q] = e < e1 ? a.in_src[e] : -1;
+      }
+      double t[kGU];
+#pragma unroll
+      for (int q = 0; q < kGU; ++q) t[q] = src[q] >= 0 ? (double)xs[src[q]] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kGU; ++q) {
+        const int64_t e = e00 + (int64_t)q * kBlock;
+        if (kWeighted && src[q] >= 0) t[q] *= a.in_w[e];
+        acc += t[q];
+      }
     }
     acc = block_sum(acc, s_red);
     if (threadIdx.x == 0) finish_row(r0, acc);
   } else {
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-      double t = (double)xs[a.in_src[e]];
-      if (kWeighted) t *= a.in_w[e];
-      s_val[e - e0] = t;
+    for (int64_t e00 = e0 + threadIdx.x; e00 < e1; e00 += kGU * kBlock) {
+      int32_t src[kGU];
+#pragma unroll
+      for (int q = 0; q < kGU; ++q) {
+        const int64_t e = e00 + (int64_t)q * kBlock;
+        src[q] = e < e1 ? a.in_src[e] : -1;
+      }
+      double t[kGU];
+#pragma unroll
+      for (int q = 0; q < kGU; ++q) t[q] = src[q] >= 0 ? (double)xs[src[q]] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kGU; ++q) {
+        const int64_t e = e00 + (int64_t)q * kBlock;
+        if (src[q] >= 0) s_val[e - e0] = kWeighted ? t[q] * a.in_w[e] : t[q];
+      }
     }
     __syncthreads();
     const int r = r0 + threadIdx.x;
@@ -144,6 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(PowArgs<G> a, int k) {
       finish_row(r, acc);
     }
   }
+  (void)gather;
   diff = block_sum(diff, s_red);
   if (threadIdx.x == 0 && diff != 0.0) unsafeAtomicAdd(&ctl->acc[k % 3][blockIdx.x & 255], diff);
 }
@@ -232,12 +266,25 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
   k_pow_init<G><<<grid_n, kBlock, 0, s>>>(a);
   DI_HIP(hipGetLastError());
   PowCtl* h = ws.hctl.as<PowCtl>();
+  LaunchTimer lt(s, (o->flags & DI_TIMING) != 0);
   int k = 0;
   int chunk = 16;
   for (;;) {
     for (int i = 0; i < chunk; ++i, ++k) {
-      if (g->weighted) k_pull<G, true><<<(int)g->npull, kBlock, 0, s>>>(a, k);
-      else k_pull<G, false><<<(int)g->npull, kBlock, 0, s>>>(a, k);
+      if (lt.on) {
+        hipEvent_t e0, e1;
+        lt.next(&e0, &e1);
+        if (g->weighted)
+          hipExtLaunchKernelGGL(k_pull<G, true>, dim3((int)g->npull), dim3(kBlock), 0, s, e0, e1,
+                                0, a, k);
+        else
+          hipExtLaunchKernelGGL(k_pull<G, false>, dim3((int)g->npull), dim3(kBlock), 0, s, e0,
+                                e1, 0, a, k);
+      } else if (g->weighted) {
+        k_pull<G, true><<<(int)g->npull, kBlock, 0, s>>>(a, k);
+      } else {
+        k_pull<G, false><<<(int)g->npull, kBlock, 0, s>>>(a, k);
+      }
       DI_HIP(hipGetLastError());
     }
     DI_HIP(hipMemcpyAsync(h, ws.ctl.p, sizeof(PowCtl), hipMemcpyDeviceToHost, s));
@@ -283,6 +330,9 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
     st->rounds = K + (delta ? 1 : 0);
     st->nodes_diffused = (int64_t)K * n;
     st->edges_diffused = (int64_t)K * g->m;
+    // launches 0..K-1 compute products; launch K only detects the stop.
+    st->kernel_seconds = lt.on ? lt.total((size_t)K) : 0.0;
+    st->kernel_launches = lt.on ? (int64_t)K : 0;
   }
   if (h->reason == 2) {
     set_error("non-finite residual");

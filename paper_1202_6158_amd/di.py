@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ------------------------------------------------------------------ constants
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EAGAIN, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 FP32_FLUID, FP64 = 0, 1
-DEVICE_PTRS, RESUME = 1, 2
+DEVICE_PTRS, RESUME, TIMING = 1, 2, 4
 SCHED_MEAN, SCHED_OP2, SCHED_OP = 0, 1, 2
 PRECISION = {"fp32": FP32_FLUID, "fp64": FP64, FP32_FLUID: FP32_FLUID, FP64: FP64}
 SCHEDULE = {"mean": SCHED_MEAN, "op2": SCHED_OP2, "op": SCHED_OP}
@@ -57,7 +57,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("residual_l1", ctypes.c_double), ("err_bound_l1", ctypes.c_double),
                 ("mass_drift", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("rounds", ctypes.c_int64), ("nodes_diffused", ctypes.c_int64),
-                ("edges_diffused", ctypes.c_int64)]
+                ("edges_diffused", ctypes.c_int64), ("kernel_seconds", ctypes.c_double),
+                ("kernel_launches", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -233,7 +234,8 @@ def _device_vec(v, n):
 
 
 def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=True,
-          max_rounds=0, tune=None, out=None, state=None, stream=None, allow_notconv=False):
+          max_rounds=0, tune=None, out=None, state=None, stream=None, allow_notconv=False,
+          timing=False):
     """D-iteration solve on the device.  v: None (uniform), numpy or torch cuda
     float64[n].  Returns (x: torch cuda float64[n], stats dict).  With
     state=(F, H) (torch cuda tensors, F float32/float64 per precision, H
@@ -242,7 +244,7 @@ def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=Tr
     n = graph.n
     x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
     vd = _device_vec(v, n)
-    flags = DEVICE_PTRS
+    flags = DEVICE_PTRS | (TIMING if timing else 0)
     o = make_opts(d, tol, precision, normalize, max_rounds, tune, flags)
     if state is not None:
         o.flags |= RESUME
@@ -258,13 +260,14 @@ def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=Tr
 
 
 def power_solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp64", normalize=True,
-                max_rounds=0, out=None, stream=None, allow_notconv=False):
+                max_rounds=0, out=None, stream=None, allow_notconv=False, timing=False):
     """Power-iteration comparator (pull SpMV) on the device."""
     torch = _torch()
     n = graph.n
     x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
     vd = _device_vec(v, n)
-    o = make_opts(d, tol, precision, normalize, max_rounds, None, DEVICE_PTRS)
+    o = make_opts(d, tol, precision, normalize, max_rounds, None,
+                  DEVICE_PTRS | (TIMING if timing else 0))
     st = Stats()
     rc = _lib.di_power_solve(graph.handle, _ptr(vd), ctypes.byref(o), _ptr(x), ctypes.byref(st),
                              _stream(stream))
