@@ -36,9 +36,9 @@
 namespace di {
 
 struct Workspace {
-  int precision = 0, wlog = 0, nb = 0;
+  int precision = 0, wlog = 0, nb = 0, nvec = 0;
   int64_t n = 0, m = 0;
-  DevBuf F, H, v, x, bstart, ctl;
+  DevBuf F, H, v, x, bstart, ctl, flacc, active;
   DevBuf pairs[2], cnt[2], slots;
   DevBuf soff, soffT, capT;  // nb x nb segment tables
   PinnedBuf hctl;
@@ -57,12 +57,17 @@ struct DiArgs {
   const int32_t* soff;    // [w][s] segment (s -> w) start within w's region
   const int32_t* soffT;   // [s][w] the same, source-major
   const int32_t* capT;    // [s][w] segment (s -> w) size = links from window s to window w
-  T* F;
-  double* H;
-  PairT<T>* pairs[2];
-  int32_t* cnt[2];        // [w][s] records written into segment (s -> w) in a round
-  Slot* slots;            // [3][kSlots] round sums, round r uses set r % 3
-  Ctl* ctl;
+  // Per-vector state; vector vb (blockIdx.y) is at the given offsets.
+  T* F;                   // [nvec][n]
+  double* H;              // [nvec][n]
+  PairT<T>* pairs[2];     // [nvec][mrec] records of even / odd rounds
+  int32_t* cnt[2];        // [nvec][w][s] records written into segment (s -> w) in a round
+  Slot* slots;            // [nvec][3][kSlots] round sums, round r uses set r % 3
+  uint8_t* active;        // [nvec][nb] window held fluid after its last round
+  Ctl* ctl;               // [nvec]
+  double* flacc;          // [nvec][1024] flush partial sums
+  int64_t mrec;           // records per vector buffer
+  int nvec;
   double d, tol, c, theta0;
   int64_t max_rounds;
   int weighted;
@@ -126,25 +131,32 @@ __global__ void k_transpose(int nb, const int32_t* __restrict__ E, const int32_t
 
 // ------------------------------------------------------------------ kernels
 
-// F = (1-d) V (V == NULL: uniform) and H = 0 unless resuming; control reset.
+// F = (1-d) V (V == NULL: uniform) and H = 0 unless resuming, for vector
+// blockIdx.y; control, round sums and window activity reset.  seeds != NULL
+// (batches): F starts at zero and k_seed adds the seed fluid afterwards.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init(DiArgs<T> a, const double* __restrict__ v,
-                                                 int resume) {
+                                                 int resume, int seeded) {
+  const int vb = blockIdx.y;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  T* F = a.F + (int64_t)vb * a.n;
+  double* H = a.H + (int64_t)vb * a.n;
   if (!resume) {
     const double u = 1.0 / (double)a.n;
     for (int64_t i = t; i < a.n; i += stride) {
-      a.F[i] = (T)((1.0 - a.d) * (v ? v[i] : u));
-      a.H[i] = 0.0;
+      F[i] = seeded ? (T)0 : (T)((1.0 - a.d) * (v ? v[i] : u));
+      H[i] = 0.0;
     }
   }
+  Slot* slots = a.slots + (int64_t)vb * 3 * kSlots;
   for (int64_t k = t; k < 3 * kSlots; k += stride) {
-    for (int f = 0; f < kSums; ++f) a.slots[k].sum[f] = 0.0;
-    a.slots[k].mrem = 0;
+    for (int f = 0; f < kSums; ++f) slots[k].sum[f] = 0.0;
+    slots[k].mrem = 0;
   }
+  for (int64_t w = t; w < a.nb; w += stride) a.active[(int64_t)vb * a.nb + w] = seeded ? 0 : 1;
   if (t == 0) {
-    Ctl* c = a.ctl;
+    Ctl* c = a.ctl + vb;
     c->stop_round = -1;
     c->reason = 0;
     c->err = 0;
@@ -153,6 +165,21 @@ __global__ __launch_bounds__(kBlock) void k_init(DiArgs<T> a, const double* __re
     c->nodes_total = c->edges_total = 0;
     c->last_taken = c->last_edges = 0;
     for (int k = 0; k < 4; ++k) c->fl[k] = 0.0;
+  }
+}
+
+// Seed fluid of a batch: vector b holds (1-d) w_k on seeds[ptr[b]..ptr[b+1])
+// (w == NULL: uniform over the set); their windows start active.
+template <typename T>
+__global__ void k_seed(DiArgs<T> a, const int64_t* __restrict__ ptr, const int32_t* __restrict__ seeds,
+                       const double* __restrict__ w) {
+  const int vb = blockIdx.x;
+  const int64_t s0 = ptr[vb], s1 = ptr[vb + 1];
+  for (int64_t k = s0 + threadIdx.x; k < s1; k += blockDim.x) {
+    const int32_t i = seeds[k];
+    const double wt = w ? w[k] : 1.0 / (double)(s1 - s0);
+    a.F[(int64_t)vb * a.n + i] = (T)((1.0 - a.d) * wt);
+    a.active[(int64_t)vb * a.nb + (i >> a.wlog)] = 1;
   }
 }
 
@@ -205,10 +232,15 @@ constexpr int kNPT = kSuper / kRT;  // nodes per thread per pass
 template <typename T, int SCHED>
 __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_round(DiArgs<T> a, int r,
                                                                                    int mode) {
-  Ctl* ctl = a.ctl;
+  const int vb = blockIdx.y;  // vector of a batch (0 for a single solve)
+  Ctl* ctl = a.ctl + vb;
   // Launch r itself records stop_round = r-1; an earlier stop ends this launch.
   const int sr = ld_relaxed(&ctl->stop_round);
   if (sr >= 0 && sr < r - 1) return;
+  T* const Fv = a.F + (int64_t)vb * a.n;
+  double* const Hv = a.H + (int64_t)vb * a.n;
+  Slot* const slots = a.slots + (int64_t)vb * 3 * kSlots;
+  const int64_t nb2 = (int64_t)a.nb * a.nb;
 
   extern __shared__ __align__(16) unsigned char smem[];
   const int W = 1 << a.wlog;
@@ -236,9 +268,10 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
   for (int k = 0; k < kWinPer; ++k) {
     const int q = tid + k * kRT;
-    fv[k] = q < wn ? a.F[j0 + q] : (T)0;
+    fv[k] = q < wn ? Fv[j0 + q] : (T)0;
   }
-  const int32_t* cnt_in = a.cnt[(r - 1) & 1] + (int64_t)b * nb;
+  const int was_active = a.active[(int64_t)vb * nb + b];
+  const int32_t* cnt_in = a.cnt[(r - 1) & 1] + vb * nb2 + (int64_t)b * nb;
   int32_t c_own = 0, o_own = 0;  // first pass over sources (nb <= kRT in the common case)
   if (r >= 1 && tid < nb) {
     c_own = cnt_in[tid];
@@ -249,7 +282,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   double theta = a.theta0;
   bool stop = mode == 1;
   if (r >= 1) {
-    const Slot* P = a.slots + ((r - 1) % 3) * kSlots;
+    const Slot* P = slots + ((r - 1) % 3) * kSlots;
     double v[kSums] = {0, 0, 0, 0, 0, 0, 0};  // nf, snd, sd, ssc, nnz, taken, edges
     double mrem = 0.0;
     if (tid < kSlots) {
@@ -259,7 +292,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       mrem = __longlong_as_double((long long)p.mrem);
     }
     if (b == 0 && tid < kSlots) {  // set (r+1) % 3 is next used by launch r+1
-      Slot* z = a.slots + ((r + 1) % 3) * kSlots + tid;
+      Slot* z = slots + ((r + 1) % 3) * kSlots + tid;
 #pragma unroll
       for (int f = 0; f < kSums; ++f) z->sum[f] = 0.0;
       z->mrem = 0;
@@ -301,7 +334,8 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const int q = tid + k * kRT;
     if (q < wn) win[q] = (double)fv[k];
   }
-  for (int q = tid + kWinPer * kRT; q < wn; q += kRT) win[q] = (double)a.F[j0 + q];
+  for (int q = tid + kWinPer * kRT; q < wn; q += kRT) win[q] = (double)Fv[j0 + q];
+  long long total = 0;  // records addressed to this window in round r-1
   if (r >= 1) {
     if (tid < nb) {
       s_pre[tid] = c_own;
@@ -312,8 +346,17 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       s_soff[s] = a.soff[(int64_t)b * nb + s];
     }
     __syncthreads();
-    const long long total = lds_exscan<kRT>(s_pre, nb, s_scr);
-    const PairT<T>* pr = a.pairs[(r - 1) & 1];
+    total = lds_exscan<kRT>(s_pre, nb, s_scr);
+  }
+  int32_t* cnt_out = a.cnt[r & 1] + vb * nb2;  // destination-major: these stores are posted
+  if (total == 0 && !was_active) {
+    // Nothing held and nothing arrived: the window sends nothing this round.
+    if (!stop)
+      for (int w = tid; w < nb; w += kRT) cnt_out[(int64_t)w * nb + b] = 0;
+    return;
+  }
+  if (total > 0) {
+    const PairT<T>* pr = a.pairs[(r - 1) & 1] + (int64_t)vb * a.mrec;
     const int64_t base = a.bstart[b];
     for (long long i0 = tid; i0 < total; i0 += kU * kRT) {
       int64_t idx[kU];
@@ -337,7 +380,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   }
   __syncthreads();
   if (stop) {
-    for (int q = tid; q < wn; q += kRT) a.F[j0 + q] = (T)win[q];
+    for (int q = tid; q < wn; q += kRT) Fv[j0 + q] = (T)win[q];
     return;
   }
 
@@ -348,7 +391,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     s_cap[w] = a.capT[(int64_t)b * nb + w];
   }
   __syncthreads();
-  PairT<T>* out = a.pairs[r & 1];
+  PairT<T>* out = a.pairs[r & 1] + (int64_t)vb * a.mrec;
   const uint32_t wmask = (uint32_t)W - 1u;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // nf, snd, sd, ssc, nnz, taken, edges
   double mrem = 0.0;
@@ -384,14 +427,14 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       const int64_t j = j0 + t0 + tid + u * kRT;
       rs[u] = a.row_ptr[j];
       dgs[u] = a.deg[j];
-      h[u] = a.H[j];
+      h[u] = Hv[j];
     }
     long long npush = 0, nedge = 0;
 #pragma unroll
     for (int u = 0; u < kNPT; ++u) {
       if (!tk[u]) continue;
       const int q = t0 + tid + u * kRT;
-      a.H[j0 + q] = h[u] + f[u];
+      Hv[j0 + q] = h[u] + f[u];
       win[q] = 0.0;
       acc[5] += 1.0;
       if (dgs[u] > 0) {
@@ -459,9 +502,8 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     acc[6] += (double)etile;  // uniform: counted once below (thread 0 only)
     __syncthreads();
   }
-  int32_t* cnt_out = a.cnt[r & 1];  // destination-major: these stores are posted
   for (int w = tid; w < nb; w += kRT) cnt_out[(int64_t)w * nb + b] = s_pre[w];
-  for (int q = tid; q < wn; q += kRT) a.F[j0 + q] = (T)win[q];
+  for (int q = tid; q < wn; q += kRT) Fv[j0 + q] = (T)win[q];
 
   // 4. This window's sums, added into its slot.
   const double edges = acc[6];
@@ -469,7 +511,9 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   block_reduce_k<kRT, kSums>(acc, mrem, s_red);
   if (tid == 0) {
     acc[6] = edges;
-    Slot* sl = a.slots + (r % 3) * kSlots + (b % kSlots);
+    // the window stays active while some node keeps untaken fluid
+    a.active[(int64_t)vb * nb + b] = acc[4] > acc[5] ? 1 : 0;
+    Slot* sl = slots + (r % 3) * kSlots + (b % kSlots);
 #pragma unroll
     for (int f = 0; f < kSums; ++f)
       if (acc[f] != 0.0) unsafeAtomicAdd(&sl->sum[f], acc[f]);
@@ -477,15 +521,18 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   }
 }
 
-// Flush sums: sum(H+F), sum(H), sum(F), sum over dangling nodes of H, as
-// per-block partials spread over 256 slots of acc.
+// Flush sums of vector blockIdx.y: sum(H+F), sum(H), sum(F), sum over
+// dangling nodes of H, as per-block partials spread over 256 slots.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_flush_sum(DiArgs<T> a, double* __restrict__ acc) {
+__global__ __launch_bounds__(kBlock) void k_flush_sum(DiArgs<T> a) {
   __shared__ double s_red[kBlock / 64];
+  const int vb = blockIdx.y;
+  const T* F = a.F + (int64_t)vb * a.n;
+  const double* H = a.H + (int64_t)vb * a.n;
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
        i += (int64_t)gridDim.x * kBlock) {
-    const double h = a.H[i], f = (double)a.F[i];
+    const double h = H[i], f = (double)F[i];
     s0 += h + f;
     s1 += h;
     s2 += f;
@@ -496,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_flush_sum(DiArgs<T> a, double* __res
   s2 = block_sum(s2, s_red);
   s3 = block_sum(s3, s_red);
   if (threadIdx.x == 0) {
-    double* slot = acc + 4 * (blockIdx.x & 255);
+    double* slot = a.flacc + (int64_t)vb * 1024 + 4 * (blockIdx.x & 255);
     unsafeAtomicAdd(slot + 0, s0);
     unsafeAtomicAdd(slot + 1, s1);
     unsafeAtomicAdd(slot + 2, s2);
@@ -504,12 +551,14 @@ __global__ __launch_bounds__(kBlock) void k_flush_sum(DiArgs<T> a, double* __res
   }
 }
 
-// Reduce the 256 flush slots into ctl->fl (one block).
-__global__ __launch_bounds__(kBlock) void k_flush_reduce(const double* __restrict__ acc, Ctl* ctl) {
+// Reduce the 256 flush slots of vector blockIdx.x into its ctl->fl.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flush_reduce(DiArgs<T> a) {
   __shared__ double s_red[kBlock / 64];
+  const double* acc = a.flacc + (int64_t)blockIdx.x * 1024;
   for (int k = 0; k < 4; ++k) {
     const double v = block_sum(acc[4 * threadIdx.x + k], s_red);
-    if (threadIdx.x == 0) ctl->fl[k] = v;
+    if (threadIdx.x == 0) a.ctl[blockIdx.x].fl[k] = v;
   }
 }
 
@@ -517,81 +566,83 @@ __global__ __launch_bounds__(kBlock) void k_flush_reduce(const double* __restric
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_flush_write(DiArgs<T> a, double* __restrict__ x,
                                                         int normalize) {
-  const double s = normalize ? a.ctl->fl[0] : 1.0;
+  const int vb = blockIdx.y;
+  const T* F = a.F + (int64_t)vb * a.n;
+  const double* H = a.H + (int64_t)vb * a.n;
+  const double s = normalize ? a.ctl[vb].fl[0] : 1.0;
+  double* xv = x + (int64_t)vb * a.n;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
        i += (int64_t)gridDim.x * kBlock)
-    x[i] = (a.H[i] + (double)a.F[i]) / s;
+    xv[i] = (H[i] + (double)F[i]) / s;
 }
 
-__global__ void k_zero(double* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_zero(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
 }
 
 // --------------------------------------------------------------- workspace
 
-static double* flush_slots(Workspace* ws) {
-  return reinterpret_cast<double*>(reinterpret_cast<char*>(ws->ctl.p) + 1024);
+// Device bytes one vector of a solve holds (state, records, counts, sums).
+static int64_t bytes_per_vector(int64_t n, int64_t m, int nb, int precision) {
+  const int64_t fs = precision == DI_FP64 ? 8 : 4, ps = precision == DI_FP64 ? 16 : 8;
+  return n * (fs + 8) + 2 * std::max<int64_t>(m, 1) * ps + 2 * (int64_t)nb * nb * 4 +
+         3 * kSlots * (int64_t)sizeof(Slot) + nb + (int64_t)sizeof(Ctl) + 1024 * 8;
 }
 
-Workspace* acquire_workspace(Graph* g, int precision, int wlog) {
-  {
-    std::lock_guard<std::mutex> lk(g->ws_mu);
-    for (size_t i = 0; i < g->ws_free.size(); ++i) {
-      Workspace* ws = g->ws_free[i];
-      if (ws->precision == precision && ws->wlog == wlog) {
-        g->ws_free.erase(g->ws_free.begin() + i);
-        return ws;
-      }
-    }
-  }
+// Workspace for nvec vectors of window 2^wlog (single solves use nvec = 1).
+static Workspace* make_workspace(Graph* g, int precision, int wlog, int nvec) {
   auto* ws = new Workspace();
   try {
-    const int64_t n = g->n, m = g->m;
+    const int64_t n = g->n, m = g->m, mrec = std::max<int64_t>(m, 1);
     const size_t fs = precision == DI_FP64 ? 8 : 4;
     const int nb = (int)((n + (1ll << wlog) - 1) >> wlog);
     const int64_t nb2 = (int64_t)nb * nb;
-    static_assert(sizeof(Ctl) <= 1024, "control block layout");
     ws->precision = precision;
     ws->wlog = wlog;
     ws->nb = nb;
+    ws->nvec = nvec;
     ws->n = n;
     ws->m = m;
-    ws->F.alloc(n * fs);
-    ws->H.alloc(n * 8);
-    ws->v.alloc(n * 8);
-    ws->x.alloc(n * 8);
-    ws->bstart.alloc((nb + 1) * 8);
-    ws->ctl.alloc(1024 + 1024 * 8);  // Ctl, then 256 x 4 flush slots
-    for (int k = 0; k < 2; ++k) {
-      ws->pairs[k].alloc(std::max<int64_t>(m, 1) * (precision == DI_FP64 ? 16 : 8));
-      ws->cnt[k].alloc(nb2 * 4);
+    ws->F.alloc(nvec * n * fs);
+    ws->H.alloc(nvec * n * 8);
+    if (nvec == 1) {
+      ws->v.alloc(n * 8);
+      ws->x.alloc(n * 8);
     }
-    ws->slots.alloc(3 * kSlots * sizeof(Slot));
+    ws->bstart.alloc((nb + 1) * 8);
+    ws->ctl.alloc(nvec * sizeof(Ctl));
+    ws->flacc.alloc(nvec * 1024 * 8);
+    ws->active.alloc(nvec * (int64_t)nb);
+    for (int k = 0; k < 2; ++k) {
+      ws->pairs[k].alloc(nvec * mrec * (precision == DI_FP64 ? 16 : 8));
+      ws->cnt[k].alloc(nvec * nb2 * 4);
+    }
+    ws->slots.alloc(nvec * 3 * kSlots * sizeof(Slot));
     ws->soff.alloc(nb2 * 4);
     ws->soffT.alloc(nb2 * 4);
     ws->capT.alloc(nb2 * 4);
-    ws->hctl.alloc(sizeof(Ctl));
-    DevBuf E;
+    ws->hctl.alloc(nvec * sizeof(Ctl));
+    DevBuf E, err;
     E.alloc(nb2 * 4);
+    err.alloc(sizeof(int));
     DI_HIP(hipMemset(E.p, 0, nb2 * 4));
-    DI_HIP(hipMemset(ws->ctl.p, 0, sizeof(Ctl)));
+    DI_HIP(hipMemset(err.p, 0, sizeof(int)));
     const int gn = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
     k_window_links<<<gn, 256>>>(n, wlog, nb, g->row_ptr.as<int64_t>(), g->col.as<int32_t>(),
                                 E.as<int32_t>());
     DI_HIP(hipGetLastError());
     k_segments<<<nb, kBlock>>>(n, wlog, nb, g->in_ptr.as<int64_t>(), E.as<int32_t>(),
-                               ws->soff.as<int32_t>(), ws->bstart.as<int64_t>(),
-                               &ws->ctl.as<Ctl>()->err);
+                               ws->soff.as<int32_t>(), ws->bstart.as<int64_t>(), err.as<int>());
     DI_HIP(hipGetLastError());
     const int gt = (int)std::max<int64_t>(1, std::min<int64_t>((nb2 + 255) / 256, 4096));
     k_transpose<<<gt, 256>>>(nb, E.as<int32_t>(), ws->soff.as<int32_t>(), ws->soffT.as<int32_t>(),
                              ws->capT.as<int32_t>());
     DI_HIP(hipGetLastError());
     DI_HIP(hipDeviceSynchronize());
-    Ctl h;
-    DI_HIP(hipMemcpy(&h, ws->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost));
-    if (h.err) {
+    int h_err = 0;
+    DI_HIP(hipMemcpy(&h_err, err.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (h_err) {
       set_error("window segment tables do not match the in-link counts");
       throw Fail{DI_EDEVICE};
     }
@@ -600,6 +651,44 @@ Workspace* acquire_workspace(Graph* g, int precision, int wlog) {
     throw;
   }
   return ws;
+}
+
+Workspace* acquire_workspace(Graph* g, int precision, int wlog) {
+  {
+    std::lock_guard<std::mutex> lk(g->ws_mu);
+    for (size_t i = 0; i < g->ws_free.size(); ++i) {
+      Workspace* ws = g->ws_free[i];
+      if (ws->precision == precision && ws->wlog == wlog && ws->nvec == 1) {
+        g->ws_free.erase(g->ws_free.begin() + i);
+        return ws;
+      }
+    }
+  }
+  return make_workspace(g, precision, wlog, 1);
+}
+
+// A workspace for at least nvec vectors (batches); reuses a cached one.
+static Workspace* acquire_batch_workspace(Graph* g, int precision, int wlog, int nvec) {
+  {
+    std::lock_guard<std::mutex> lk(g->ws_mu);
+    for (size_t i = 0; i < g->ws_free.size(); ++i) {
+      Workspace* ws = g->ws_free[i];
+      if (ws->precision == precision && ws->wlog == wlog && ws->nvec >= nvec && ws->nvec > 1) {
+        g->ws_free.erase(g->ws_free.begin() + i);
+        return ws;
+      }
+    }
+    // drop cached batch workspaces of other shapes before allocating a large one
+    for (size_t i = 0; i < g->ws_free.size();) {
+      if (g->ws_free[i]->nvec > 1) {
+        delete g->ws_free[i];
+        g->ws_free.erase(g->ws_free.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+  }
+  return make_workspace(g, precision, wlog, nvec);
 }
 
 void release_workspace(Graph* g, Workspace* ws) {
@@ -629,7 +718,7 @@ struct WsGuard {
 
 template <typename T>
 static DiArgs<T> make_args(const Graph* g, Workspace* ws, double d, double tol, double c,
-                           int64_t max_rounds, T* F, double* H) {
+                           int64_t max_rounds, T* F, double* H, int nvec) {
   DiArgs<T> a;
   memset(&a, 0, sizeof(a));
   a.n = g->n;
@@ -648,12 +737,16 @@ static DiArgs<T> make_args(const Graph* g, Workspace* ws, double d, double tol, 
   a.capT = ws->capT.as<int32_t>();
   a.F = F;
   a.H = H;
+  a.mrec = std::max<int64_t>(g->m, 1);
   for (int k = 0; k < 2; ++k) {
     a.pairs[k] = ws->pairs[k].as<PairT<T>>();
     a.cnt[k] = ws->cnt[k].as<int32_t>();
   }
   a.slots = ws->slots.as<Slot>();
+  a.active = ws->active.as<uint8_t>();
   a.ctl = ws->ctl.as<Ctl>();
+  a.flacc = ws->flacc.as<double>();
+  a.nvec = nvec;
   a.d = d;
   a.tol = tol;
   a.c = c;
@@ -683,14 +776,14 @@ static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, L
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_limit));
   }
   DI_REQUIRE(smem <= dyn_limit, "window tables exceed the LDS available to the round kernel");
+  const dim3 grid(a.nb, a.nvec);
   if (lt && lt->on) {
     // The runtime stamps the kernel's own begin/end into the event pair.
     hipEvent_t e0, e1;
     lt->next(&e0, &e1);
-    hipExtLaunchKernelGGL(k_round<T, SCHED>, dim3(a.nb), dim3(kRT), smem, s, e0, e1, 0, a, r,
-                          mode);
+    hipExtLaunchKernelGGL(k_round<T, SCHED>, grid, dim3(kRT), smem, s, e0, e1, 0, a, r, mode);
   } else {
-    k_round<T, SCHED><<<a.nb, kRT, smem, s>>>(a, r, mode);
+    k_round<T, SCHED><<<grid, kRT, smem, s>>>(a, r, mode);
   }
   DI_HIP(hipGetLastError());
 }
@@ -705,13 +798,14 @@ static void launch_round(const DiArgs<T>& a, int sched, int r, int mode, hipStre
   }
 }
 
-static void read_ctl(Workspace* ws, hipStream_t s) {
-  DI_HIP(hipMemcpyAsync(ws->hctl.p, ws->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+static void read_ctl(Workspace* ws, int nvec, hipStream_t s) {
+  DI_HIP(hipMemcpyAsync(ws->hctl.p, ws->ctl.p, nvec * sizeof(Ctl), hipMemcpyDeviceToHost, s));
   DI_HIP(hipStreamSynchronize(s));
 }
 
-// Launches rounds until a launch records the stop (that launch also folds the
-// last pushes, so (F, H) is again a state of the recurrences).
+// Launches rounds until every vector's launch has recorded its stop (that
+// launch also folds the last pushes, so (F, H) is again a state of the
+// recurrences).
 template <typename T>
 static void run_rounds(const DiArgs<T>& a, Workspace* ws, int sched, int check_every,
                        hipStream_t s, LaunchTimer* lt) {
@@ -722,32 +816,40 @@ static void run_rounds(const DiArgs<T>& a, Workspace* ws, int sched, int check_e
   int r_prev = 0;
   for (;;) {
     for (int i = 0; i < chunk; ++i) launch_round(a, sched, r++, 0, s, lt);
-    read_ctl(ws, s);
-    if (h->stop_round >= 0) break;
+    read_ctl(ws, a.nvec, s);
+    double nf_max = 0.0;
+    bool all = true;
+    for (int v = 0; v < a.nvec; ++v) {
+      if (h[v].stop_round < 0) {
+        all = false;
+        nf_max = std::max(nf_max, h[v].nf);
+      }
+    }
+    if (all) break;
     if (check_every == 0) {
-      // Predict the rounds left from the observed per-round decay of ||F||_1.
+      // Predict the rounds left from the observed per-round decay of ||F||_1
+      // of the slowest vector.
       int next = 8;
-      if (nf_prev > 0.0 && h->nf > 0.0 && h->nf < nf_prev && r > r_prev) {
-        const double q = std::pow(h->nf / nf_prev, 1.0 / (r - r_prev));
+      if (nf_prev > 0.0 && nf_max > 0.0 && nf_max < nf_prev && r > r_prev) {
+        const double q = std::pow(nf_max / nf_prev, 1.0 / (r - r_prev));
         if (q > 0.0 && q < 1.0)
-          next = (int)std::ceil(std::log(a.tol / h->nf) / std::log(q) * 1.15) + 2;
+          next = (int)std::ceil(std::log(a.tol / nf_max) / std::log(q) * 1.15) + 2;
       }
       chunk = std::max(2, std::min(next, 64));
-      nf_prev = h->nf;
+      nf_prev = nf_max;
       r_prev = r;
     }
   }
 }
 
 template <typename T>
-static void flush(const DiArgs<T>& a, Workspace* ws, double* x, int normalize, hipStream_t s) {
-  double* acc = flush_slots(ws);
-  k_zero<<<4, 256, 0, s>>>(acc, 1024);
+static void flush(const DiArgs<T>& a, double* x, int normalize, hipStream_t s) {
+  k_zero<<<(int)((a.nvec * 1024 + 255) / 256), 256, 0, s>>>(a.flacc, (int64_t)a.nvec * 1024);
   DI_HIP(hipGetLastError());
-  const int grid = grid_for(a.n, 1024);
-  k_flush_sum<T><<<grid, kBlock, 0, s>>>(a, acc);
+  const dim3 grid(grid_for(a.n, 1024), a.nvec);
+  k_flush_sum<T><<<grid, kBlock, 0, s>>>(a);
   DI_HIP(hipGetLastError());
-  k_flush_reduce<<<1, kBlock, 0, s>>>(acc, a.ctl);
+  k_flush_reduce<T><<<a.nvec, kBlock, 0, s>>>(a);
   DI_HIP(hipGetLastError());
   if (x) {
     k_flush_write<T><<<grid, kBlock, 0, s>>>(a, x, normalize);
@@ -755,22 +857,63 @@ static void flush(const DiArgs<T>& a, Workspace* ws, double* x, int normalize, h
   }
 }
 
+static void fill_stats(const Ctl& h, const di_opts* o, double secs, di_stats* st) {
+  const double d = o->d;
+  const double S = h.fl[0], nf = h.fl[2];
+  st->residual_l1 = nf;
+  st->err_bound_l1 = o->normalize ? (S > 0 ? 2.0 * d * nf / ((1.0 - d) * S) : 0.0)
+                                  : d * nf / (1.0 - d);
+  st->mass_drift = h.fl[1] + (h.fl[2] + d * h.fl[3]) / (1.0 - d) - 1.0;
+  st->seconds = secs;
+  st->rounds = h.stop_round + 1;
+  st->nodes_diffused = h.nodes_total;
+  st->edges_diffused = h.edges_total;
+  st->kernel_seconds = 0.0;
+  st->kernel_launches = 0;
+}
+
+static di_status status_of(const Ctl& h) {
+  if (h.err) {
+    set_error("internal segment consistency check failed (code " + std::to_string(h.err) + ")");
+    return DI_EDEVICE;
+  }
+  if (h.reason == 2) {
+    set_error("non-finite residual");
+    return DI_EDEVICE;
+  }
+  if (h.reason == 3) {
+    set_error("max_rounds reached before ||F||_1 < tol");
+    return DI_ENOTCONV;
+  }
+  return DI_OK;
+}
+
+struct TuneParams {
+  int sched, wlog, check_every;
+  double c;
+};
+
+static TuneParams tune_params(const Graph* g, const di_tune* tn) {
+  TuneParams p;
+  p.sched = tn ? tn->schedule : DI_SCHED_MEAN;
+  DI_REQUIRE(p.sched >= 0 && p.sched <= 2, "unknown schedule");
+  p.c = (tn && tn->c > 0.f) ? (double)tn->c : 1.0;
+  p.wlog = window_log2_for(g->n, tn ? tn->window_log2 : 0);
+  DI_REQUIRE(p.wlog > 0, "graph has too many nodes for the window tables");
+  p.check_every = tn ? std::max(0, tn->check_every) : 0;
+  return p;
+}
+
 template <typename T>
 static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double* x,
                             di_stats* st, hipStream_t s) {
-  const di_tune* tn = o->tune;
-  const int sched = tn ? tn->schedule : DI_SCHED_MEAN;
-  DI_REQUIRE(sched >= 0 && sched <= 2, "unknown schedule");
-  const double c = (tn && tn->c > 0.f) ? (double)tn->c : 1.0;
-  const int wlog = window_log2_for(g->n, tn ? tn->window_log2 : 0);
-  DI_REQUIRE(wlog > 0, "graph has too many nodes for the window tables");
-  const int check_every = tn ? std::max(0, tn->check_every) : 0;
+  const TuneParams tp = tune_params(g, o->tune);
   const bool dev = (o->flags & DI_DEVICE_PTRS) != 0;
   const bool resume = (o->flags & DI_RESUME) != 0;
   const int64_t max_rounds = o->max_rounds > 0 ? o->max_rounds : 1000000;
   DI_REQUIRE(!resume || (o->state_f && o->state_h), "DI_RESUME needs state_f and state_h");
   if (v && !dev) validate_vector(v, g->n, "v");
-  WsGuard guard{g, acquire_workspace(g, o->precision, wlog), s};
+  WsGuard guard{g, acquire_workspace(g, o->precision, tp.wlog), s};
   Workspace* ws = guard.ws;
   const double* vdev = nullptr;
   if (v) {
@@ -783,47 +926,107 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   }
   T* F = resume ? static_cast<T*>(o->state_f) : ws->F.as<T>();
   double* H = resume ? o->state_h : ws->H.as<double>();
-  DiArgs<T> a = make_args<T>(g, ws, o->d, o->tol, c, max_rounds, F, H);
+  DiArgs<T> a = make_args<T>(g, ws, o->d, o->tol, tp.c, max_rounds, F, H, 1);
   LaunchTimer lt(s, (o->flags & DI_TIMING) != 0);
   EventTimer timer(s);
-  k_init<T><<<grid_for(g->n, 2048), kBlock, 0, s>>>(a, vdev, resume ? 1 : 0);
+  k_init<T><<<dim3(grid_for(g->n, 2048), 1), kBlock, 0, s>>>(a, vdev, resume ? 1 : 0, 0);
   DI_HIP(hipGetLastError());
-  run_rounds(a, ws, sched, check_every, s, &lt);
+  run_rounds(a, ws, tp.sched, tp.check_every, s, &lt);
   double* xo = x ? (dev ? x : ws->x.as<double>()) : nullptr;
-  flush(a, ws, xo, o->normalize, s);
+  flush(a, xo, o->normalize, s);
   const double secs = timer.stop();
   if (x && !dev) DI_HIP(hipMemcpyAsync(x, xo, g->n * 8, hipMemcpyDeviceToHost, s));
-  read_ctl(ws, s);
+  read_ctl(ws, 1, s);
   const Ctl* h = ws->hctl.as<Ctl>();
   if (st) {
-    const double d = o->d;
-    const double S = h->fl[0], nf = h->fl[2];
-    st->residual_l1 = nf;
-    st->err_bound_l1 = o->normalize ? (S > 0 ? 2.0 * d * nf / ((1.0 - d) * S) : 0.0)
-                                    : d * nf / (1.0 - d);
-    st->mass_drift = h->fl[1] + (h->fl[2] + d * h->fl[3]) / (1.0 - d) - 1.0;
-    st->seconds = secs;
-    st->rounds = h->stop_round + 1;
-    st->nodes_diffused = h->nodes_total;
-    st->edges_diffused = h->edges_total;
+    fill_stats(*h, o, secs, st);
     // launches 0..stop_round take and expand; launch stop_round+1 folds.
     const size_t working = (size_t)h->stop_round + 2;
     st->kernel_seconds = lt.on ? lt.total(working) : 0.0;
     st->kernel_launches = lt.on ? (int64_t)working : 0;
   }
-  if (h->err) {
-    set_error("internal segment consistency check failed (code " + std::to_string(h->err) + ")");
-    return DI_EDEVICE;
+  return status_of(*h);
+}
+
+template <typename T>
+static di_status batch_impl(Graph* g, int32_t B, const int64_t* seed_ptr, const int32_t* seeds,
+                            const double* seed_w, const di_opts* o, double* x, di_stats* st,
+                            hipStream_t s) {
+  const TuneParams tp = tune_params(g, o->tune);
+  const bool dev = (o->flags & DI_DEVICE_PTRS) != 0;
+  const int64_t n = g->n;
+  const int64_t max_rounds = o->max_rounds > 0 ? o->max_rounds : 1000000;
+  // Validation of the seed sets (host arrays).
+  DI_REQUIRE(B >= 1, "B must be >= 1");
+  DI_REQUIRE(seed_ptr && seeds, "seed_ptr and seeds are required");
+  DI_REQUIRE(seed_ptr[0] == 0, "seed_ptr[0] must be 0");
+  {
+    std::vector<int32_t> tmp;
+    for (int32_t b = 0; b < B; ++b) {
+      DI_REQUIRE(seed_ptr[b + 1] > seed_ptr[b], "empty seed set");
+      tmp.assign(seeds + seed_ptr[b], seeds + seed_ptr[b + 1]);
+      double ws = 0.0;
+      for (int64_t k = seed_ptr[b]; k < seed_ptr[b + 1]; ++k) {
+        DI_REQUIRE(seeds[k] >= 0 && seeds[k] < n, "seed out of range");
+        if (seed_w) {
+          DI_REQUIRE(std::isfinite(seed_w[k]) && seed_w[k] >= 0.0,
+                     "seed weight negative or not finite");
+          ws += seed_w[k];
+        }
+      }
+      if (seed_w) DI_REQUIRE(std::fabs(ws - 1.0) <= 1e-9, "seed weights of a set must sum to 1");
+      std::sort(tmp.begin(), tmp.end());
+      DI_REQUIRE(std::adjacent_find(tmp.begin(), tmp.end()) == tmp.end(), "repeated seed in a set");
+    }
   }
-  if (h->reason == 2) {
-    set_error("non-finite residual");
-    return DI_EDEVICE;
+  // Vectors per group: what 80% of the free device memory holds.
+  size_t free_b = 0, total_b = 0;
+  DI_HIP(hipMemGetInfo(&free_b, &total_b));
+  const int nb = (int)((n + (1ll << tp.wlog) - 1) >> tp.wlog);
+  const int64_t per = bytes_per_vector(n, g->m, nb, o->precision);
+  int group = (int)std::max<int64_t>(1, std::min<int64_t>(B, (int64_t)(0.8 * (double)free_b) / per));
+  WsGuard guard{g, acquire_batch_workspace(g, o->precision, tp.wlog, std::max(group, 2)), s};
+  Workspace* ws = guard.ws;
+  group = std::min(group, ws->nvec);
+  DevBuf d_ptr, d_seeds, d_w, d_x;
+  const int64_t nseeds = seed_ptr[B];
+  d_ptr.alloc((B + 1) * 8);
+  d_seeds.alloc(nseeds * 4);
+  if (seed_w) d_w.alloc(nseeds * 8);
+  if (x && !dev) d_x.alloc((int64_t)group * n * 8);
+  di_status worst = DI_OK;
+  for (int32_t b0 = 0; b0 < B; b0 += group) {
+    const int gb = std::min<int32_t>(group, B - b0);
+    // seed pointers of this group, rebased to 0
+    std::vector<int64_t> ptr(gb + 1);
+    for (int k = 0; k <= gb; ++k) ptr[k] = seed_ptr[b0 + k] - seed_ptr[b0];
+    DI_HIP(hipMemcpyAsync(d_ptr.p, ptr.data(), (gb + 1) * 8, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemcpyAsync(d_seeds.p, seeds + seed_ptr[b0], ptr[gb] * 4, hipMemcpyHostToDevice, s));
+    if (seed_w)
+      DI_HIP(hipMemcpyAsync(d_w.p, seed_w + seed_ptr[b0], ptr[gb] * 8, hipMemcpyHostToDevice, s));
+    DiArgs<T> a = make_args<T>(g, ws, o->d, o->tol, tp.c, max_rounds, ws->F.as<T>(),
+                               ws->H.as<double>(), gb);
+    EventTimer timer(s);
+    k_init<T><<<dim3(grid_for(n, 256), gb), kBlock, 0, s>>>(a, nullptr, 0, 1);
+    DI_HIP(hipGetLastError());
+    k_seed<T><<<gb, 256, 0, s>>>(a, d_ptr.as<int64_t>(), d_seeds.as<int32_t>(),
+                                  seed_w ? d_w.as<double>() : nullptr);
+    DI_HIP(hipGetLastError());
+    run_rounds(a, ws, tp.sched, tp.check_every, s, nullptr);
+    double* xo = x ? (dev ? x + (int64_t)b0 * n : d_x.as<double>()) : nullptr;
+    flush(a, xo, o->normalize, s);
+    const double secs = timer.stop();
+    if (x && !dev)
+      DI_HIP(hipMemcpyAsync(x + (int64_t)b0 * n, xo, (int64_t)gb * n * 8, hipMemcpyDeviceToHost, s));
+    read_ctl(ws, gb, s);
+    const Ctl* h = ws->hctl.as<Ctl>();
+    for (int k = 0; k < gb; ++k) {
+      if (st) fill_stats(h[k], o, secs, &st[b0 + k]);
+      const di_status rc = status_of(h[k]);
+      if (rc == DI_EDEVICE || (rc == DI_ENOTCONV && worst == DI_OK)) worst = rc;
+    }
   }
-  if (h->reason == 3) {
-    set_error("max_rounds reached before ||F||_1 < tol");
-    return DI_ENOTCONV;
-  }
-  return DI_OK;
+  return worst;
 }
 
 template <typename T>
@@ -835,13 +1038,13 @@ static void round_impl(Graph* g, double d, double theta, T* F, double* H, int64_
                 acquire_workspace(g, std::is_same<T, double>::value ? DI_FP64 : DI_FP32_FLUID, wlog),
                 s};
   Workspace* ws = guard.ws;
-  DiArgs<T> a = make_args<T>(g, ws, d, 0.0, 1.0, (int64_t)1 << 40, F, H);
+  DiArgs<T> a = make_args<T>(g, ws, d, 0.0, 1.0, (int64_t)1 << 40, F, H, 1);
   a.theta0 = theta;
-  k_init<T><<<grid_for(g->n, 2048), kBlock, 0, s>>>(a, nullptr, 1);
+  k_init<T><<<dim3(grid_for(g->n, 2048), 1), kBlock, 0, s>>>(a, nullptr, 1, 0);
   DI_HIP(hipGetLastError());
   launch_round(a, DI_SCHED_MEAN, 0, 0, s);
   launch_round(a, DI_SCHED_MEAN, 1, 1, s);
-  read_ctl(ws, s);
+  read_ctl(ws, 1, s);
   const Ctl* h = ws->hctl.as<Ctl>();
   if (h->err) {
     set_error("internal segment consistency check failed");
@@ -867,6 +1070,23 @@ di_status di_solve(const di_graph* gc, const double* v, const di_opts* opts, dou
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = opts->precision == DI_FP64 ? solve_impl<double>(g, v, opts, x, stats, s)
                                     : solve_impl<float>(g, v, opts, x, stats, s);
+  });
+  return g != DI_OK ? g : rc;
+}
+
+di_status di_solve_batch(const di_graph* gc, int32_t B, const int64_t* seed_ptr,
+                         const int32_t* seeds, const double* seed_w, const di_opts* opts,
+                         double* x, di_stats* stats, void* stream) {
+  di_status rc = DI_OK;
+  di_status g = guarded([&] {
+    DI_REQUIRE(gc != nullptr, "graph is NULL");
+    validate_d_tol(opts);
+    DI_REQUIRE((opts->flags & DI_RESUME) == 0, "DI_RESUME is not supported for batches");
+    Graph* g = const_cast<di_graph*>(gc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = opts->precision == DI_FP64
+             ? batch_impl<double>(g, B, seed_ptr, seeds, seed_w, opts, x, stats, s)
+             : batch_impl<float>(g, B, seed_ptr, seeds, seed_w, opts, x, stats, s);
   });
   return g != DI_OK ? g : rc;
 }

@@ -5,11 +5,6 @@ using namespace di;
 
 extern "C" {
 
-di_status di_solve_batch(const di_graph*, int32_t, const int64_t*, const int32_t*, const double*,
-                         const di_opts*, double*, di_stats*, void*) {
-  set_error("di_solve_batch: not built yet");
-  return DI_EINVAL;
-}
 di_status di_server_create(const di_server_opts*, di_server**) {
   set_error("server: not built yet");
   return DI_EINVAL;
