@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(PKG_DIR, "libdi.so")
 
 
 def build(verbose: bool = False) -> str:
-    from . import build as _b
+    from . import compile_lib as _b
     return _b.build(verbose=verbose)
 
 

@@ -68,6 +68,13 @@ struct DiArgs {
   double* flacc;          // [nvec][1024] flush partial sums
   int64_t mrec;           // records per vector buffer
   int nvec;
+  // Serving: blockIdx.y -> vector slot, and per-slot round index, d and tol
+  // (NULL for solves and batches, which use blockIdx.y, the launch's round
+  // index and the common d / tol).
+  const int32_t* vmap;
+  const int32_t* vround;
+  const double* vd;
+  const double* vtol;
   double d, tol, c, theta0;
   int64_t max_rounds;
   int weighted;
@@ -137,7 +144,8 @@ __global__ void k_transpose(int nb, const int32_t* __restrict__ E, const int32_t
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init(DiArgs<T> a, const double* __restrict__ v,
                                                  int resume, int seeded) {
-  const int vb = blockIdx.y;
+  const int vb = a.vmap ? a.vmap[blockIdx.y] : blockIdx.y;
+  const double dv = a.vd ? a.vd[vb] : a.d;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   T* F = a.F + (int64_t)vb * a.n;
@@ -145,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DiArgs<T> a, const double* __re
   if (!resume) {
     const double u = 1.0 / (double)a.n;
     for (int64_t i = t; i < a.n; i += stride) {
-      F[i] = seeded ? (T)0 : (T)((1.0 - a.d) * (v ? v[i] : u));
+      F[i] = seeded ? (T)0 : (T)((1.0 - dv) * (v ? v[i] : u));
       H[i] = 0.0;
     }
   }
@@ -173,12 +181,13 @@ __global__ __launch_bounds__(kBlock) void k_init(DiArgs<T> a, const double* __re
 template <typename T>
 __global__ void k_seed(DiArgs<T> a, const int64_t* __restrict__ ptr, const int32_t* __restrict__ seeds,
                        const double* __restrict__ w) {
-  const int vb = blockIdx.x;
-  const int64_t s0 = ptr[vb], s1 = ptr[vb + 1];
+  const int vb = a.vmap ? a.vmap[blockIdx.x] : blockIdx.x;
+  const double dv = a.vd ? a.vd[vb] : a.d;
+  const int64_t s0 = ptr[blockIdx.x], s1 = ptr[blockIdx.x + 1];
   for (int64_t k = s0 + threadIdx.x; k < s1; k += blockDim.x) {
     const int32_t i = seeds[k];
     const double wt = w ? w[k] : 1.0 / (double)(s1 - s0);
-    a.F[(int64_t)vb * a.n + i] = (T)((1.0 - a.d) * wt);
+    a.F[(int64_t)vb * a.n + i] = (T)((1.0 - dv) * wt);
     a.active[(int64_t)vb * a.nb + (i >> a.wlog)] = 1;
   }
 }
@@ -232,7 +241,10 @@ constexpr int kNPT = kSuper / kRT;  // nodes per thread per pass
 template <typename T, int SCHED>
 __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_round(DiArgs<T> a, int r,
                                                                                    int mode) {
-  const int vb = blockIdx.y;  // vector of a batch (0 for a single solve)
+  const int vb = a.vmap ? a.vmap[blockIdx.y] : blockIdx.y;  // vector (0 for a single solve)
+  if (a.vround) r = a.vround[vb];
+  const double d = a.vd ? a.vd[vb] : a.d;
+  const double tol = a.vtol ? a.vtol[vb] : a.tol;
   Ctl* ctl = a.ctl + vb;
   // Launch r itself records stop_round = r-1; an earlier stop ends this launch.
   const int sr = ld_relaxed(&ctl->stop_round);
@@ -302,12 +314,12 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                  edges = v[6];
     int reason = 0;
     if (!isfinite(nf)) reason = 2;
-    else if (nf < a.tol) reason = 1;
+    else if (nf < tol) reason = 1;
     else if ((int64_t)r >= a.max_rounds) reason = 3;
     if (reason) stop = true;
     // Remaining fluid after round r-1's pushes, in exact arithmetic: the
     // non-dangling senders keep d of what they send, the dangling ones none.
-    const double R = nf - (1.0 - a.d) * snd - sd;
+    const double R = nf - (1.0 - d) * snd - sd;
     // theta_r: c times the mean score of the nodes holding fluid, scaled by
     // the predicted decay of the total fluid.  After a round that took
     // nothing, fall back to the largest untaken score (at least the mean,
@@ -455,7 +467,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       const long long dg = dgs[u];
       s_beo[slot] = (int32_t)eoff;
       s_brow[slot] = rs[u];
-      s_bsh[slot] = a.weighted ? a.d * f[u] : a.d * f[u] / (double)dg;
+      s_bsh[slot] = a.weighted ? d * f[u] : d * f[u] / (double)dg;
       ++slot;
       eoff += dg;
     }
@@ -526,7 +538,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_flush_sum(DiArgs<T> a) {
   __shared__ double s_red[kBlock / 64];
-  const int vb = blockIdx.y;
+  const int vb = a.vmap ? a.vmap[blockIdx.y] : blockIdx.y;
   const T* F = a.F + (int64_t)vb * a.n;
   const double* H = a.H + (int64_t)vb * a.n;
   double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -555,10 +567,11 @@ __global__ __launch_bounds__(kBlock) void k_flush_sum(DiArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_flush_reduce(DiArgs<T> a) {
   __shared__ double s_red[kBlock / 64];
-  const double* acc = a.flacc + (int64_t)blockIdx.x * 1024;
+  const int vb = a.vmap ? a.vmap[blockIdx.x] : blockIdx.x;
+  const double* acc = a.flacc + (int64_t)vb * 1024;
   for (int k = 0; k < 4; ++k) {
     const double v = block_sum(acc[4 * threadIdx.x + k], s_red);
-    if (threadIdx.x == 0) a.ctl[blockIdx.x].fl[k] = v;
+    if (threadIdx.x == 0) a.ctl[vb].fl[k] = v;
   }
 }
 
@@ -566,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void k_flush_reduce(DiArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_flush_write(DiArgs<T> a, double* __restrict__ x,
                                                         int normalize) {
-  const int vb = blockIdx.y;
+  const int vb = a.vmap ? a.vmap[blockIdx.y] : blockIdx.y;
   const T* F = a.F + (int64_t)vb * a.n;
   const double* H = a.H + (int64_t)vb * a.n;
   const double s = normalize ? a.ctl[vb].fl[0] : 1.0;
@@ -842,9 +855,16 @@ static void run_rounds(const DiArgs<T>& a, Workspace* ws, int sched, int check_e
   }
 }
 
+// Zero the flush slots of the vectors of this launch (slot vmap[blockIdx.x]).
+template <typename T>
+__global__ void k_zero_flush(DiArgs<T> a) {
+  const int vb = a.vmap ? a.vmap[blockIdx.x] : blockIdx.x;
+  for (int k = threadIdx.x; k < 1024; k += blockDim.x) a.flacc[(int64_t)vb * 1024 + k] = 0.0;
+}
+
 template <typename T>
 static void flush(const DiArgs<T>& a, double* x, int normalize, hipStream_t s) {
-  k_zero<<<(int)((a.nvec * 1024 + 255) / 256), 256, 0, s>>>(a.flacc, (int64_t)a.nvec * 1024);
+  k_zero_flush<T><<<a.nvec, 256, 0, s>>>(a);
   DI_HIP(hipGetLastError());
   const dim3 grid(grid_for(a.n, 1024), a.nvec);
   k_flush_sum<T><<<grid, kBlock, 0, s>>>(a);
@@ -1052,6 +1072,312 @@ static void round_impl(Graph* g, double d, double theta, T* F, double* H, int64_
   }
   if (tn) *tn = h->last_taken;
   if (te) *te = h->last_edges;
+}
+
+// ------------------------------------------------------------------ top-k
+
+constexpr int kTopBins = 2048;  // key prefix histogram (non-negative float bits >> shift)
+
+// Histogram of key prefixes of x = H + F for slot vmap[blockIdx.y]; with
+// parent >= 0 only keys whose (key >> 20) equals parent are counted.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_topk_hist(DiArgs<T> a, int shift, const int* parent,
+                                                      int32_t* __restrict__ hist) {
+  __shared__ int32_t h[kTopBins];
+  for (int k = threadIdx.x; k < kTopBins; k += kBlock) h[k] = 0;
+  __syncthreads();
+  const int y = blockIdx.y, vb = a.vmap[y];
+  const T* F = a.F + (int64_t)vb * a.n;
+  const double* H = a.H + (int64_t)vb * a.n;
+  const int par = parent ? parent[y] : -1;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const uint32_t key = __float_as_uint((float)(H[i] + (double)F[i]));
+    if (par >= 0 && (int)(key >> 20) != par) continue;
+    atomicAdd(&h[(key >> shift) & (kTopBins - 1)], 1);
+  }
+  __syncthreads();
+  int32_t* gh = hist + (int64_t)y * kTopBins;
+  for (int k = threadIdx.x; k < kTopBins; k += kBlock)
+    if (h[k]) atomicAdd(&gh[k], h[k]);
+}
+
+// Candidates: every i whose key >> 9 is at least thr[y] (a key prefix of 23 bits).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_topk_collect(DiArgs<T> a, const uint32_t* thr,
+                                                         double* __restrict__ cval,
+                                                         int32_t* __restrict__ cid,
+                                                         int32_t* __restrict__ ccount, int cap) {
+  const int y = blockIdx.y, vb = a.vmap[y];
+  const T* F = a.F + (int64_t)vb * a.n;
+  const double* H = a.H + (int64_t)vb * a.n;
+  const uint32_t t = thr[y];
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < a.n; i0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = i0 + threadIdx.x;
+    double x = 0.0;
+    bool take = false;
+    if (i < a.n) {
+      x = H[i] + (double)F[i];
+      take = (__float_as_uint((float)x) >> 9) >= t;
+    }
+    // one reservation per wave
+    const unsigned long long m = __ballot(take);
+    if (m == 0) continue;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == __ffsll((long long)m) - 1) base = atomicAdd(&ccount[y], __popcll(m));
+    base = __shfl(base, __ffsll((long long)m) - 1, 64);
+    if (take) {
+      const int pos = base + __popcll(m & ((1ull << lane) - 1));
+      if (pos < cap) {
+        cval[(int64_t)y * cap + pos] = x;
+        cid[(int64_t)y * cap + pos] = (int32_t)i;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------- serving engine
+
+int64_t slot_bytes(const Graph* g, int precision) {
+  const int wlog = window_log2_for(g->n, 0);
+  const int nb = (int)((g->n + (1ll << wlog) - 1) >> wlog);
+  return bytes_per_vector(g->n, g->m, nb, precision);
+}
+
+template <typename T>
+class SlotPoolT : public SlotPool {
+ public:
+  SlotPoolT(Graph* g, int precision, int capacity, const di_tune* tune) : g_(g), cap_(capacity) {
+    tp_ = tune_params(g, tune);
+    ws_ = make_workspace(g, precision, tp_.wlog, capacity);
+    round_.assign(capacity, 0);
+    d_.assign(capacity, 0.85);
+    tol_.assign(capacity, 1e-6);
+    vmap_.alloc(capacity * 4);
+    vround_.alloc(capacity * 4);
+    vd_.alloc(capacity * 8);
+    vtol_.alloc(capacity * 8);
+    h_vmap_.alloc(capacity * 4);
+    h_vround_.alloc(capacity * 4);
+    h_vd_.alloc(capacity * 8);
+    h_vtol_.alloc(capacity * 8);
+    hist_.alloc((int64_t)capacity * kTopBins * 4);
+    h_hist_.alloc((int64_t)capacity * kTopBins * 4);
+    par_.alloc(capacity * 4);
+    h_par_.alloc(capacity * 4);
+    thr_.alloc(capacity * 4);
+    h_thr_.alloc(capacity * 4);
+    ccount_.alloc(capacity * 4);
+    h_ccount_.alloc(capacity * 4);
+    cval_.alloc((int64_t)capacity * kCap * 8);
+    cid_.alloc((int64_t)capacity * kCap * 4);
+    h_cval_.alloc((int64_t)capacity * kCap * 8);
+    h_cid_.alloc((int64_t)capacity * kCap * 4);
+  }
+  ~SlotPoolT() override { delete ws_; }
+  int capacity() const override { return cap_; }
+  int64_t bytes() const override {
+    return (int64_t)cap_ * bytes_per_vector(g_->n, g_->m, ws_->nb, ws_->precision);
+  }
+
+  void admit(const std::vector<SlotInit>& inits, hipStream_t s) override {
+    if (inits.empty()) return;
+    const int k = (int)inits.size();
+    std::vector<int64_t> ptr(k + 1, 0);
+    std::vector<int32_t> seeds;
+    std::vector<double> w;
+    bool weighted = false;
+    for (const SlotInit& in : inits) weighted |= !in.w.empty();
+    int32_t* hv = h_vmap_.as<int32_t>();
+    for (int q = 0; q < k; ++q) {
+      const SlotInit& in = inits[q];
+      hv[q] = in.slot;
+      round_[in.slot] = 0;
+      d_[in.slot] = in.d;
+      tol_[in.slot] = in.tol;
+      seeds.insert(seeds.end(), in.seeds.begin(), in.seeds.end());
+      if (weighted) {
+        if (in.w.empty()) w.insert(w.end(), in.seeds.size(), 1.0 / (double)in.seeds.size());
+        else w.insert(w.end(), in.w.begin(), in.w.end());
+      }
+      ptr[q + 1] = (int64_t)seeds.size();
+    }
+    sptr_.alloc((k + 1) * 8);
+    sseeds_.alloc(seeds.size() * 4);
+    h_sptr_.alloc((k + 1) * 8);
+    h_sseeds_.alloc(seeds.size() * 4);
+    memcpy(h_sptr_.p, ptr.data(), (k + 1) * 8);
+    memcpy(h_sseeds_.p, seeds.data(), seeds.size() * 4);
+    if (weighted) {
+      sw_.alloc(w.size() * 8);
+      h_sw_.alloc(w.size() * 8);
+      memcpy(h_sw_.p, w.data(), w.size() * 8);
+    }
+    memcpy(h_vd_.p, d_.data(), cap_ * 8);
+    memcpy(h_vtol_.p, tol_.data(), cap_ * 8);
+    DI_HIP(hipMemcpyAsync(vmap_.p, h_vmap_.p, k * 4, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemcpyAsync(vd_.p, h_vd_.p, cap_ * 8, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemcpyAsync(vtol_.p, h_vtol_.p, cap_ * 8, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemcpyAsync(sptr_.p, h_sptr_.p, (k + 1) * 8, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemcpyAsync(sseeds_.p, h_sseeds_.p, seeds.size() * 4, hipMemcpyHostToDevice, s));
+    if (weighted) DI_HIP(hipMemcpyAsync(sw_.p, h_sw_.p, w.size() * 8, hipMemcpyHostToDevice, s));
+    DiArgs<T> a = args(k);
+    k_init<T><<<dim3(grid_for(g_->n, 256), k), kBlock, 0, s>>>(a, nullptr, 0, 1);
+    DI_HIP(hipGetLastError());
+    k_seed<T><<<k, 256, 0, s>>>(a, sptr_.as<int64_t>(), sseeds_.as<int32_t>(),
+                                 weighted ? sw_.as<double>() : nullptr);
+    DI_HIP(hipGetLastError());
+    // the staging buffers above are reused by the next call: drain first
+    DI_HIP(hipStreamSynchronize(s));
+  }
+
+  void step(const std::vector<int>& slots, hipStream_t s) override {
+    if (slots.empty()) return;
+    const int k = (int)slots.size();
+    int32_t* hv = h_vmap_.as<int32_t>();
+    int32_t* hr = h_vround_.as<int32_t>();
+    for (int q = 0; q < k; ++q) hv[q] = slots[q];
+    for (int q = 0; q < cap_; ++q) hr[q] = round_[q];
+    DI_HIP(hipMemcpyAsync(vmap_.p, h_vmap_.p, k * 4, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemcpyAsync(vround_.p, h_vround_.p, cap_ * 4, hipMemcpyHostToDevice, s));
+    DiArgs<T> a = args(k);
+    a.vround = vround_.as<int32_t>();
+    launch_round(a, tp_.sched, 0, 0, s);
+    for (int q : slots) ++round_[q];
+  }
+
+  std::vector<int> stopped(const std::vector<int>& slots, hipStream_t s) override {
+    read_ctl(ws_, cap_, s);
+    const Ctl* h = ws_->hctl.as<Ctl>();
+    std::vector<int> out;
+    for (int q : slots)
+      if (h[q].stop_round >= 0) out.push_back(q);
+    return out;
+  }
+
+  void finish(const std::vector<int>& slots, int topk, std::vector<SlotResult>& out,
+              hipStream_t s) override {
+    if (slots.empty()) return;
+    const int k = (int)slots.size();
+    int32_t* hv = h_vmap_.as<int32_t>();
+    for (int q = 0; q < k; ++q) hv[q] = slots[q];
+    DI_HIP(hipMemcpyAsync(vmap_.p, h_vmap_.p, k * 4, hipMemcpyHostToDevice, s));
+    DiArgs<T> a = args(k);
+    flush(a, nullptr, 1, s);
+    // key-prefix histogram (bits 30..20), then, where needed, the next 11 bits
+    const int gx = grid_for(g_->n, 512);
+    k_zero32(hist_.as<int32_t>(), (int64_t)k * kTopBins, s);
+    k_topk_hist<T><<<dim3(gx, k), kBlock, 0, s>>>(a, 20, nullptr, hist_.as<int32_t>());
+    DI_HIP(hipGetLastError());
+    DI_HIP(hipMemcpyAsync(h_hist_.p, hist_.p, (int64_t)k * kTopBins * 4, hipMemcpyDeviceToHost, s));
+    read_ctl(ws_, cap_, s);
+    const int32_t* hh = h_hist_.as<int32_t>();
+    int32_t* par = h_par_.as<int32_t>();
+    uint32_t* thr = h_thr_.as<uint32_t>();
+    const int kk = (int)std::min<int64_t>(topk, g_->n);
+    bool refine = false;
+    std::vector<int64_t> above(k, 0);
+    for (int q = 0; q < k; ++q) {
+      const int32_t* h = hh + (int64_t)q * kTopBins;
+      int64_t cum = 0;
+      int b = kTopBins - 1;
+      for (; b > 0; --b) {
+        if (cum + h[b] >= kk) break;
+        cum += h[b];
+      }
+      // fewer than kk non-zero entries: take every non-zero one (bins >= 1)
+      par[q] = b >= 1 && cum + h[b] > kCap ? b : -1;
+      above[q] = cum;
+      thr[q] = (uint32_t)std::max(b, 1) << 11;  // key >> 9 >= b << 11  <=>  key >> 20 >= b
+      if (par[q] >= 0) refine = true;
+    }
+    if (refine) {
+      DI_HIP(hipMemcpyAsync(par_.p, h_par_.p, k * 4, hipMemcpyHostToDevice, s));
+      k_zero32(hist_.as<int32_t>(), (int64_t)k * kTopBins, s);
+      k_topk_hist<T><<<dim3(gx, k), kBlock, 0, s>>>(a, 9, par_.as<int32_t>(), hist_.as<int32_t>());
+      DI_HIP(hipGetLastError());
+      DI_HIP(hipMemcpyAsync(h_hist_.p, hist_.p, (int64_t)k * kTopBins * 4, hipMemcpyDeviceToHost,
+                            s));
+      DI_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < k; ++q) {
+        if (par[q] < 0) continue;
+        const int32_t* h = hh + (int64_t)q * kTopBins;
+        int64_t cum = above[q];
+        int b = kTopBins - 1;
+        for (; b > 0; --b) {
+          if (cum + h[b] >= kk) break;
+          cum += h[b];
+        }
+        thr[q] = ((uint32_t)par[q] << 11) | (uint32_t)b;
+      }
+    }
+    DI_HIP(hipMemcpyAsync(thr_.p, h_thr_.p, k * 4, hipMemcpyHostToDevice, s));
+    k_zero32(ccount_.as<int32_t>(), k, s);
+    k_topk_collect<T><<<dim3(gx, k), kBlock, 0, s>>>(a, thr_.as<uint32_t>(), cval_.as<double>(),
+                                                      cid_.as<int32_t>(), ccount_.as<int32_t>(),
+                                                      kCap);
+    DI_HIP(hipGetLastError());
+    DI_HIP(hipMemcpyAsync(h_ccount_.p, ccount_.p, k * 4, hipMemcpyDeviceToHost, s));
+    DI_HIP(hipMemcpyAsync(h_cval_.p, cval_.p, (int64_t)k * kCap * 8, hipMemcpyDeviceToHost, s));
+    DI_HIP(hipMemcpyAsync(h_cid_.p, cid_.p, (int64_t)k * kCap * 4, hipMemcpyDeviceToHost, s));
+    read_ctl(ws_, cap_, s);
+    const Ctl* hc = ws_->hctl.as<Ctl>();
+    const int32_t* cc = h_ccount_.as<int32_t>();
+    for (int q = 0; q < k; ++q) {
+      const int slot = slots[q];
+      const Ctl& c = hc[slot];
+      SlotResult r;
+      r.slot = slot;
+      r.status = status_of(c);
+      const int nc = std::min(cc[q], kCap);
+      std::vector<std::pair<double, int32_t>> v(nc);
+      for (int t = 0; t < nc; ++t)
+        v[t] = {h_cval_.as<double>()[(int64_t)q * kCap + t], h_cid_.as<int32_t>()[(int64_t)q * kCap + t]};
+      std::sort(v.begin(), v.end(), [](const auto& x, const auto& y) {
+        return x.first > y.first || (x.first == y.first && x.second < y.second);
+      });
+      const double S = c.fl[0];
+      for (int t = 0; t < nc && t < kk; ++t) {
+        r.ids.push_back(v[t].second);
+        r.x.push_back(S > 0 ? v[t].first / S : 0.0);
+      }
+      const double d = d_[slot], nf = c.fl[2];
+      r.residual = nf;
+      r.bound = S > 0 ? 2.0 * d * nf / ((1.0 - d) * S) : 0.0;
+      r.rounds = c.stop_round + 1;
+      r.edges = c.edges_total;
+      out.push_back(std::move(r));
+    }
+  }
+
+ private:
+  static constexpr int kCap = 8192;  // candidates kept per slot
+  DiArgs<T> args(int k) {
+    DiArgs<T> a = make_args<T>(g_, ws_, 0.85, 1e-6, tp_.c, 1000000, ws_->F.as<T>(),
+                               ws_->H.as<double>(), k);
+    a.vmap = vmap_.as<int32_t>();
+    a.vd = vd_.as<double>();
+    a.vtol = vtol_.as<double>();
+    return a;
+  }
+  static void k_zero32(int32_t* p, int64_t n, hipStream_t s) {
+    DI_HIP(hipMemsetAsync(p, 0, n * 4, s));
+  }
+  Graph* g_;
+  int cap_;
+  TuneParams tp_;
+  Workspace* ws_;
+  std::vector<int> round_;
+  std::vector<double> d_, tol_;
+  DevBuf vmap_, vround_, vd_, vtol_, hist_, par_, thr_, ccount_, cval_, cid_, sptr_, sseeds_, sw_;
+  PinnedBuf h_vmap_, h_vround_, h_vd_, h_vtol_, h_hist_, h_par_, h_thr_, h_ccount_, h_cval_, h_cid_,
+      h_sptr_, h_sseeds_, h_sw_;
+};
+
+SlotPool* make_slot_pool(Graph* g, int precision, int capacity, const di_tune* tune) {
+  if (precision == DI_FP64) return new SlotPoolT<double>(g, precision, capacity, tune);
+  return new SlotPoolT<float>(g, precision, capacity, tune);
 }
 
 }  // namespace di

@@ -148,6 +148,49 @@ Workspace* acquire_workspace(Graph* g, int precision, int wlog);
 void release_workspace(Graph* g, Workspace* ws);
 void destroy_workspace(Workspace* ws);
 
+// ------------------------------------------------------------ serving engine
+
+// One request's personalisation as the engine admits it into a slot.
+struct SlotInit {
+  int slot;
+  double d, tol;
+  std::vector<int32_t> seeds;
+  std::vector<double> w;  // empty: uniform over the seeds
+};
+
+// Result of a finished slot.
+struct SlotResult {
+  int slot;
+  int status;  // DI_OK, DI_ENOTCONV, DI_EDEVICE
+  std::vector<int32_t> ids;
+  std::vector<double> x;
+  double residual, bound;
+  int64_t rounds, edges;
+};
+
+// Device state for up to `capacity` concurrent personalised solves on one graph
+// (defined in diter.hip).  Not thread-safe: one scheduler thread drives it.
+class SlotPool {
+ public:
+  virtual ~SlotPool() = default;
+  virtual int capacity() const = 0;
+  virtual int64_t bytes() const = 0;
+  // Initialise the slots of `inits` (F = (1-d)V, H = 0, control reset).
+  virtual void admit(const std::vector<SlotInit>& inits, hipStream_t s) = 0;
+  // One round for every listed slot (each at its own round index).
+  virtual void step(const std::vector<int>& slots, hipStream_t s) = 0;
+  // Refresh the host copy of the slots' control blocks (synchronises s) and
+  // return the slots among `slots` whose solve has stopped.
+  virtual std::vector<int> stopped(const std::vector<int>& slots, hipStream_t s) = 0;
+  // Flush and top-k of finished slots (synchronises s).
+  virtual void finish(const std::vector<int>& slots, int topk, std::vector<SlotResult>& out,
+                      hipStream_t s) = 0;
+};
+
+// Bytes of one slot of a pool on g.
+int64_t slot_bytes(const Graph* g, int precision);
+SlotPool* make_slot_pool(Graph* g, int precision, int capacity, const di_tune* tune);
+
 // Validation helpers.
 void validate_d_tol(const di_opts* o);
 void validate_vector(const double* v, int64_t n, const char* what);

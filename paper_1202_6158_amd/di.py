@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdi.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libdi.so not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
-                      "or `python paper_1202_6158_amd/build.py` (expected at %s)" % LIB_PATH)
+                      "or `python paper_1202_6158_amd/compile_lib.py` (expected at %s)" % LIB_PATH)
 
 _lib = ctypes.CDLL(LIB_PATH)
 

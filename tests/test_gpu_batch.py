@@ -39,7 +39,7 @@ def test_batch_vectors_match_exact_ppr(di, c1, prec, tol, eps):
     xb = x.cpu().numpy()
     for b in range(24):
         v = wl.seed_vector(g.n, seeds[ptr[b]:ptr[b + 1]])
-        xs = oracle.sparse_exact(g, D, v)[1]
+        xs = oracle.limit(g, D, v, tol=1e-14)
         assert stats[b]["residual_l1"] < tol
         assert _l1(xb[b], xs) <= stats[b]["err_bound_l1"] + eps, b
 
@@ -67,7 +67,7 @@ def test_weighted_seeds_and_single_vector_batch(di, c1):
     x, stats = di.solve_batch(G, ptr, seeds, seed_w=w, d=D, tol=1e-12, precision="fp64")
     v = np.zeros(g.n)
     v[seeds] = w
-    xs = oracle.sparse_exact(g, D, v)[1]
+    xs = oracle.limit(g, D, v, tol=1e-14)
     assert _l1(x[0].cpu().numpy(), xs) <= stats[0]["err_bound_l1"] + 1e-12
 
 

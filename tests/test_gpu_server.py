@@ -1,0 +1,141 @@
+"""GPU tests of the continuous-batching PPR server (di_server_*): results
+against the oracle's exact personalised PageRank, the same request alone and
+in a mix, admission while other requests run, budget accounting, cancellation
+and validation."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+D = 0.85
+
+
+@pytest.fixture(scope="module")
+def di():
+    import torch
+    from paper_1202_6158_amd import di as _di
+    torch.cuda.set_device(0)
+    return _di
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    return [wl.recipe("pagerank-10k"), wl.random_small(30000, 240000, seed=8, p_dangling=0.15)]
+
+
+def check_topk(res, xs, k, eps):
+    """res: server result; xs: exact normalised PPR vector."""
+    ids, vals, b = res["top_ids"], res["top_x"], res["err_bound_l1"]
+    assert len(ids) == min(k, np.count_nonzero(xs)) or len(ids) == k
+    assert np.all(np.diff(vals) <= 0)
+    assert np.all(np.abs(vals - xs[ids]) <= b + eps)
+    if len(ids):
+        rest = np.ones(len(xs), bool)
+        rest[ids] = False
+        assert xs[rest].max(initial=0.0) <= vals[-1] + 2 * (b + eps)
+
+
+def test_server_results_match_exact_ppr(di, graphs):
+    G = [di.Graph(g) for g in graphs]
+    srv = di.Server(hbm_budget_bytes=8 << 30, max_slots=32, topk=50)
+    gid = [srv.add_graph(x) for x in G]
+    rng = np.random.default_rng(5)
+    reqs = []
+    for q in range(40):
+        gi = q % 2
+        g = graphs[gi]
+        s = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(301)))), 1, 300))
+        seeds = np.sort(rng.choice(g.n, size=s, replace=False)).astype(np.int32)
+        tol = [1e-4, 1e-6, 1e-8][q % 3]
+        reqs.append((gi, seeds, tol, srv.submit(gid[gi], seeds, d=D, tol=tol)))
+    for gi, seeds, tol, rid in reqs:
+        r = srv.wait(rid, 120.0)
+        assert r is not None and r["status"] == 0
+        assert r["residual_l1"] < tol
+        xs = oracle.limit(graphs[gi], D, wl.seed_vector(graphs[gi].n, seeds), tol=1e-14)
+        check_topk(r, xs, 50, 1e-6)
+    st = srv.stats()
+    assert st["completed"] == 40 and st["hbm_in_use"] <= st["hbm_budget"]
+    assert st["p99_latency_s"] >= st["p50_latency_s"] > 0
+    srv.close()
+
+
+def test_same_result_alone_and_in_the_mix(di, graphs):
+    g = graphs[1]
+    G = di.Graph(g)
+    seeds = np.array([3, 77, 1234, 20000], dtype=np.int32)
+    alone = di.Server(hbm_budget_bytes=4 << 30, max_slots=8, topk=100)
+    ga = alone.add_graph(G)
+    ra = alone.wait(alone.submit(ga, seeds, d=D, tol=1e-8), 60.0)
+    alone.close()
+    mix = di.Server(hbm_budget_bytes=4 << 30, max_slots=8, topk=100)
+    gm = mix.add_graph(G)
+    rng = np.random.default_rng(9)
+    others = [mix.submit(gm, np.sort(rng.choice(g.n, 20, replace=False)).astype(np.int32),
+                         d=D, tol=t) for t in [1e-4, 1e-8, 1e-6, 1e-8, 1e-4, 1e-6]]
+    target = mix.submit(gm, seeds, d=D, tol=1e-8)
+    others += [mix.submit(gm, np.sort(rng.choice(g.n, 5, replace=False)).astype(np.int32),
+                          d=D, tol=1e-6) for _ in range(6)]
+    rm = mix.wait(target, 60.0)
+    for o in others:
+        assert mix.wait(o, 60.0)["status"] == 0
+    mix.close()
+    bound = ra["err_bound_l1"] + rm["err_bound_l1"] + 2e-6
+    common = np.intersect1d(ra["top_ids"], rm["top_ids"])
+    va = dict(zip(ra["top_ids"], ra["top_x"]))
+    vm = dict(zip(rm["top_ids"], rm["top_x"]))
+    assert all(abs(va[i] - vm[i]) <= bound for i in common)
+    # entries present in only one list sit at the tail, within the bounds of the cut
+    for only, other in [(set(va) - set(vm), rm), (set(vm) - set(va), ra)]:
+        for i in only:
+            assert (va.get(i, vm.get(i))) <= other["top_x"][-1] + 2 * bound
+
+
+def test_requests_admitted_while_others_run(di, graphs):
+    """Short requests submitted while a long one runs are admitted into free
+    slots and finish before it: they share its launches instead of queueing."""
+    g = graphs[1]
+    G = di.Graph(g)
+    srv = di.Server(hbm_budget_bytes=4 << 30, max_slots=8, topk=10)
+    gid = srv.add_graph(G)
+    long_id = srv.submit(gid, np.array([1], dtype=np.int32), d=0.999, tol=1e-12)
+    t0 = time.time()
+    while srv.stats()["active"] < 1 and time.time() - t0 < 10:
+        time.sleep(1e-4)
+    short = [srv.submit(gid, np.array([100 + q], dtype=np.int32), d=D, tol=1e-4) for q in range(5)]
+    rs = [srv.wait(q, 60.0) for q in short]
+    rl = srv.wait(long_id, 120.0)
+    assert all(r["status"] == 0 for r in rs) and rl["status"] == 0
+    assert rl["residual_l1"] < 1e-12
+    assert all(rl["t_admit"] < r["t_admit"] < rl["t_done"] for r in rs)
+    assert max(r["t_done"] for r in rs) < rl["t_done"]
+    srv.close()
+
+
+def test_cancel_and_validation(di, graphs):
+    g = graphs[0]
+    G = di.Graph(g)
+    srv = di.Server(hbm_budget_bytes=2 << 30, max_slots=2, topk=10)
+    gid = srv.add_graph(G)
+    ids = [srv.submit(gid, np.array([q], dtype=np.int32), d=0.9, tol=1e-10) for q in range(6)]
+    srv.cancel(ids[-1])
+    with pytest.raises(di.DiError) as e:
+        srv.wait(ids[-1], 60.0)
+    assert e.value.status == di.ECANCELED
+    for q in ids[:-1]:
+        srv.wait(q, 120.0)
+    for bad in [dict(seeds=np.array([], np.int32)), dict(seeds=np.array([5, 5], np.int32)),
+                dict(seeds=np.array([g.n], np.int32)), dict(seeds=np.array([1], np.int32), d=1.0),
+                dict(seeds=np.array([1], np.int32), tol=0.0)]:
+        kw = dict(d=D, tol=1e-6)
+        kw.update(bad)
+        seeds = kw.pop("seeds")
+        with pytest.raises(di.DiError):
+            srv.submit(gid, seeds, **kw)
+    with pytest.raises(di.DiError):
+        srv.submit(7, np.array([1], np.int32))
+    srv.close()
