@@ -195,6 +195,123 @@ def bench_ppr_batch(di, G, g, args):
             "edges_diffused": int(sum(s["edges_diffused"] for s in stats))}
 
 
+SERVE_GRAPHS = ("serve-100k", "serve-500k", "serve-1m", "serve-5m")
+SERVE_TOLS = (1e-4, 1e-6, 1e-8)
+
+
+def _run_stream(di, srv, gids, graphs, t, gi, sizes, tol, sub, d, label):
+    """Submit requests at their arrival times (open loop); returns the results
+    in submission order and the wall time of the submission phase."""
+    import numpy as np
+    import workloads as wl
+    seeds = [wl.request_seeds(graphs[g].n, int(s), int(u)) for g, s, u in zip(gi, sizes, sub)]
+    rids = []
+    t0 = time.perf_counter()
+    next_log = 10.0
+    for k in range(len(t)):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= t[k]:
+                break
+            if t[k] - now > 2e-4:
+                time.sleep(min(t[k] - now - 1e-4, 0.01))
+        rids.append(srv.submit(gids[gi[k]], seeds[k], d=d, tol=float(tol[k])))
+        if now > next_log:
+            log("%s: %.0f s, %d submitted, %s" % (label, now, k + 1, srv.stats()["active"]))
+            next_log += 10.0
+    sub_s = time.perf_counter() - t0
+    res = []
+    for k, rid in enumerate(rids):
+        r = srv.wait(rid, 120.0)
+        if r is None:
+            raise RuntimeError("request %d did not finish within 120 s" % k)
+        res.append(r)
+    return res, sub_s
+
+
+def bench_serve(di, args):
+    """Continuous-batching server on the four resident serving graphs: an
+    open-loop Poisson stream (latency percentiles, achieved rate), a burst of
+    requests submitted at once (capacity), and the same requests one at a time
+    (a server with one slot) as the baseline the batching has to beat."""
+    import numpy as np
+    import workloads as wl
+    graphs = [wl.recipe(r) for r in SERVE_GRAPHS]
+    G = [di.Graph(g) for g in graphs]
+    srv = di.Server(hbm_budget_bytes=args.serve_hbm_gib << 30, max_slots=256, topk=100)
+    gids = [srv.add_graph(x) for x in G]
+    caps = srv.stats()["hbm_in_use"]
+    dur = args.serve_warmup + args.serve_seconds
+    t, gi, sizes, tol, sub = wl.poisson_stream(args.serve_rate, dur, len(graphs), 1000,
+                                               SERVE_TOLS, seed=5)
+    log("serve: %d requests over %.1f s at %.0f/s" % (len(t), dur, args.serve_rate))
+    res, sub_s = _run_stream(di, srv, gids, graphs, t, gi, sizes, tol, sub, args.d, "serve")
+    meas = [r for r, tk in zip(res, t) if tk >= args.serve_warmup]
+    ok = sum(r["status"] == 0 for r in res)
+    lat = np.array([r["t_done"] - r["t_submit"] for r in meas])
+    t_first = min(r["t_submit"] for r in meas)
+    t_last = max(r["t_done"] for r in meas)
+    achieved = len(meas) / (t_last - t_first)
+    per_graph = {}
+    for g in range(len(graphs)):
+        lg = np.array([r["t_done"] - r["t_submit"] for r, tk, q in zip(res, t, gi)
+                       if tk >= args.serve_warmup and q == g])
+        if len(lg):
+            per_graph[SERVE_GRAPHS[g]] = {"requests": int(len(lg)),
+                                          "p50_ms": 1e3 * float(np.percentile(lg, 50)),
+                                          "p99_ms": 1e3 * float(np.percentile(lg, 99))}
+    srv.close()
+
+    # capacity: a burst of requests with the stream's mix, all submitted at once
+    nb_ = args.serve_burst
+    tb, gib, szb, tolb, subb = wl.poisson_stream(1e9, 1.0, len(graphs), 1000, SERVE_TOLS, seed=6)
+    tb, gib, szb, tolb, subb = (x[:nb_] for x in (tb, gib, szb, tolb, subb))
+    srv = di.Server(hbm_budget_bytes=args.serve_hbm_gib << 30, max_slots=256, topk=100)
+    gids = [srv.add_graph(x) for x in G]
+    t0 = time.perf_counter()
+    rb, _ = _run_stream(di, srv, gids, graphs, np.zeros(nb_), gib, szb, tolb, subb, args.d, "burst")
+    burst_s = time.perf_counter() - t0
+    srv.close()
+
+    # one at a time: the first requests of the burst through a one-slot server
+    ns = args.serve_solo
+    srv = di.Server(hbm_budget_bytes=args.serve_hbm_gib << 30, max_slots=1, topk=100)
+    gids = [srv.add_graph(x) for x in G]
+    t0 = time.perf_counter()
+    rs, _ = _run_stream(di, srv, gids, graphs, np.zeros(ns), gib[:ns], szb[:ns], tolb[:ns],
+                        subb[:ns], args.d, "solo")
+    solo_s = time.perf_counter() - t0
+    srv.close()
+    # the same request alone and in the burst: top-k values within both bounds
+    worst = 0.0
+    for a, b in zip(rs, rb[:ns]):
+        va = dict(zip(a["top_ids"].tolist(), a["top_x"].tolist()))
+        vb = dict(zip(b["top_ids"].tolist(), b["top_x"].tolist()))
+        bound = a["err_bound_l1"] + b["err_bound_l1"]
+        for i in set(va) & set(vb):
+            worst = max(worst, abs(va[i] - vb[i]) - bound)
+    capacity = nb_ / burst_s
+    solo_qps = ns / solo_s
+    return {
+        "graphs": {n: {"n": g.n, "links": g.m} for n, g in zip(SERVE_GRAPHS, graphs)},
+        "hbm_budget_gib": args.serve_hbm_gib, "slot_bytes_total": caps,
+        "stream": {"rate_per_s": args.serve_rate, "warmup_s": args.serve_warmup,
+                   "measured_s": args.serve_seconds, "requests": len(res),
+                   "measured_requests": len(meas), "ok": ok,
+                   "submit_wall_s": sub_s, "achieved_qps": achieved,
+                   "sustained": bool(achieved >= 0.95 * args.serve_rate),
+                   "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                   "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                   "per_graph": per_graph},
+        "burst": {"requests": nb_, "seconds": burst_s, "capacity_qps": capacity,
+                  "ok": sum(r["status"] == 0 for r in rb)},
+        "one_at_a_time": {"requests": ns, "seconds": solo_s, "qps": solo_qps},
+        "speedup_vs_one_at_a_time": capacity / solo_qps,
+        "saturation_qps": None if achieved >= 0.95 * args.serve_rate else capacity,
+        "alone_vs_mix_max_excess": worst,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +324,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ppr", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
+    ap.add_argument("--serve-burst", type=int, default=2000)
+    ap.add_argument("--serve-solo", type=int, default=100)
+    ap.add_argument("--serve-hbm-gib", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -311,6 +435,8 @@ def main():
     }
     if not args.no_ppr:
         out["ppr_batch"] = bench_ppr_batch(di, G, g, args)
+    if not args.no_serve:
+        out["serve"] = bench_serve(di, args)
     if args.copy_calibration:
         out["copy_calibration_bytes"] = copy_calibration()
     if not args.no_cpu:
