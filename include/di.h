@@ -184,6 +184,44 @@ di_status di_solve_batch(const di_graph* g, int32_t B, const int64_t* seed_ptr,
                          const int32_t* seeds, const double* seed_w, const di_opts* opts,
                          double* x, di_stats* stats, void* stream);
 
+/* -------------------------------------------------------------- autotuner */
+
+#define DI_TUNE_SOLVE 0 /* tune single solves (uniform V) */
+#define DI_TUNE_BATCH 1 /* tune batched / served personalised PageRank */
+
+typedef struct di_tune_trial {
+  di_tune tune;    /* the candidate */
+  double seconds;  /* best device time per solve (DI_TUNE_BATCH: per vector) */
+  int32_t status;  /* DI_OK, or why the candidate was discarded (e.g. DI_ENOTCONV) */
+  int32_t pad;
+} di_tune_trial;
+
+/*
+ * Picks the threshold schedule (Section 4.2 threshold variant, Section 4.3
+ * OP / OP2 scores), the threshold factor c and the window size of the binned
+ * scatter for this graph by timing trial solves on the device: first every
+ * schedule x c in {0.25, 0.5, 1, 2, 4} at the default window, then the best
+ * pair at the neighbouring window sizes.  Any schedule converges to the same
+ * limit (the order independence of Section 2), so only speed is compared;
+ * candidates that do not converge within opts->max_rounds are discarded.
+ *
+ * mode DI_TUNE_SOLVE times di_solve with uniform V and opts (d, tol,
+ * precision).  DI_TUNE_BATCH times di_solve_batch on the B seed sets given
+ * (host arrays as in di_solve_batch; required) and scores seconds per vector.
+ * opts->tune and opts->flags are ignored.  Each candidate runs once untimed,
+ * then twice timed; the faster run counts.
+ *
+ * The winner is written to *best and cached in the graph per (mode,
+ * precision): later calls that pass no tune (di_solve: DI_TUNE_SOLVE;
+ * di_solve_batch and servers created afterwards: DI_TUNE_BATCH) use it.
+ * trials (may be NULL) receives up to max_trials entries; *n_trials (may be
+ * NULL) the number of candidates timed.  DI_EINVAL for bad arguments,
+ * DI_ENOTCONV if no candidate converged (nothing cached).
+ */
+di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts, int32_t B,
+                      const int64_t* seed_ptr, const int32_t* seeds, di_tune* best,
+                      di_tune_trial* trials, int32_t max_trials, int32_t* n_trials, void* stream);
+
 /* ----------------------------------------------------------------- server */
 
 typedef struct di_server_opts {

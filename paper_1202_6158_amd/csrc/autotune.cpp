@@ -1,0 +1,136 @@
+// Autotuner of the threshold schedule, threshold factor and window size.
+//
+// The D-iteration converges to the same limit whatever set of nodes each
+// round diffuses (the order independence of Section 2), so the knobs of the
+// threshold variant (Section 4.2, and the OP / OP2 scores of Section 4.3)
+// trade only speed: a low threshold diffuses more links per round and needs
+// fewer rounds, a high one wastes fewer links on small fluid.  Which side
+// wins depends on the graph and on the device's per-round latency, so the
+// tuner measures: trial solves through the public entry points, timed by the
+// library's own device events (di_stats.seconds).
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+using namespace di;
+
+namespace {
+
+struct Trial {
+  di_tune tune;
+  double seconds;
+  di_status status;
+};
+
+// Seconds per solve (per vector for batches) of one candidate: one untimed
+// run (builds the window tables of a new window size), then the faster of two.
+Trial run_candidate(const di_graph* g, int mode, const di_opts& base, int32_t B,
+                    const int64_t* seed_ptr, const int32_t* seeds, const di_tune& t,
+                    hipStream_t s) {
+  Trial out{t, std::numeric_limits<double>::infinity(), DI_OK};
+  di_opts o = base;
+  o.tune = &t;
+  o.flags = 0;
+  o.normalize = 1;
+  std::vector<di_stats> st(mode == DI_TUNE_BATCH ? B : 1);
+  for (int rep = 0; rep < 3; ++rep) {
+    const di_status rc =
+        mode == DI_TUNE_BATCH
+            ? di_solve_batch(g, B, seed_ptr, seeds, nullptr, &o, nullptr, st.data(), s)
+            : di_solve(g, nullptr, &o, nullptr, st.data(), s);
+    if (rc != DI_OK) {
+      out.status = rc;
+      return out;
+    }
+    if (rep == 0) continue;
+    // a batch reports the time of its whole group on every vector
+    const double secs = mode == DI_TUNE_BATCH ? st[0].seconds / B : st[0].seconds;
+    out.seconds = std::min(out.seconds, secs);
+  }
+  return out;
+}
+
+}  // namespace
+
+extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts, int32_t B,
+                                 const int64_t* seed_ptr, const int32_t* seeds, di_tune* best,
+                                 di_tune_trial* trials, int32_t max_trials, int32_t* n_trials,
+                                 void* stream) {
+  di_status result = DI_OK;
+  const di_status rc = guarded([&] {
+    DI_REQUIRE(g != nullptr, "graph is NULL");
+    DI_REQUIRE(mode == DI_TUNE_SOLVE || mode == DI_TUNE_BATCH, "unknown tuning mode");
+    validate_d_tol(opts);
+    DI_REQUIRE(best != nullptr, "best is NULL");
+    DI_REQUIRE(max_trials >= 0 && (max_trials == 0 || trials != nullptr),
+               "trials is NULL but max_trials > 0");
+    if (mode == DI_TUNE_BATCH)
+      DI_REQUIRE(B >= 1 && seed_ptr != nullptr && seeds != nullptr,
+                 "DI_TUNE_BATCH needs B >= 1 seed sets");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int w0 = window_log2_for(g->n, 0);
+    DI_REQUIRE(w0 > 0, "graph has too many nodes for the window tables");
+
+    std::vector<Trial> done;
+    auto run = [&](int sched, float c, int wlog) {
+      di_tune t{};
+      t.schedule = sched;
+      t.c = c;
+      t.window_log2 = wlog;
+      t.check_every = 0;
+      done.push_back(run_candidate(g, mode, *opts, B, seed_ptr, seeds, t, s));
+      return done.back();
+    };
+    auto better = [](const Trial& a, const Trial& b) {
+      if ((a.status == DI_OK) != (b.status == DI_OK)) return a.status == DI_OK;
+      return a.seconds < b.seconds;
+    };
+    // 1. schedule x threshold factor at the default window
+    const int scheds[] = {DI_SCHED_MEAN, DI_SCHED_OP2, DI_SCHED_OP};
+    const float cs[] = {0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
+    Trial win{};
+    win.status = DI_ENOTCONV;
+    win.seconds = std::numeric_limits<double>::infinity();
+    for (int sc : scheds)
+      for (float c : cs) {
+        const Trial t = run(sc, c, w0);
+        if (better(t, win)) win = t;
+      }
+    // 2. neighbouring window sizes for the best pair (sizes the LDS budget or
+    //    the window-count limit clamp to an already tried size are skipped)
+    if (win.status == DI_OK) {
+      std::vector<int> tried{w0};
+      for (int dw : {-1, 1}) {
+        const int wl = window_log2_for(g->n, w0 + dw);
+        if (wl <= 0 || std::find(tried.begin(), tried.end(), wl) != tried.end()) continue;
+        tried.push_back(wl);
+        const Trial t = run(win.tune.schedule, win.tune.c, wl);
+        if (better(t, win)) win = t;
+      }
+    }
+    const int nt = (int)done.size();
+    for (int k = 0; k < nt && k < max_trials; ++k) {
+      trials[k].tune = done[k].tune;
+      trials[k].seconds = done[k].seconds;
+      trials[k].status = done[k].status;
+      trials[k].pad = 0;
+    }
+    if (n_trials) *n_trials = nt;
+    if (win.status != DI_OK) {
+      set_error("no candidate converged within max_rounds");
+      result = DI_ENOTCONV;
+      return;
+    }
+    *best = win.tune;
+    std::lock_guard<std::mutex> lk(g->ws_mu);
+    const int pi = opts->precision == DI_FP64 ? 1 : 0;
+    g->tuned[mode][pi] = win.tune;
+    g->has_tuned[mode][pi] = true;
+  });
+  return rc != DI_OK ? rc : result;
+}

@@ -163,6 +163,13 @@ __global__ __launch_bounds__(kBlock) void k_init(DiArgs<T> a, const double* __re
     slots[k].mrem = 0;
   }
   for (int64_t w = t; w < a.nb; w += stride) a.active[(int64_t)vb * a.nb + w] = seeded ? 0 : 1;
+  // Record counts: rounds write only non-zero entries and their readers clear
+  // them, so both buffers start at zero.
+  const int64_t nb2 = (int64_t)a.nb * a.nb;
+  for (int k = 0; k < 2; ++k) {
+    int32_t* c = a.cnt[k] + vb * nb2;
+    for (int64_t q = t; q < nb2; q += stride) c[q] = 0;
+  }
   if (t == 0) {
     Ctl* c = a.ctl + vb;
     c->stop_round = -1;
@@ -246,9 +253,6 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const double d = a.vd ? a.vd[vb] : a.d;
   const double tol = a.vtol ? a.vtol[vb] : a.tol;
   Ctl* ctl = a.ctl + vb;
-  // Launch r itself records stop_round = r-1; an earlier stop ends this launch.
-  const int sr = ld_relaxed(&ctl->stop_round);
-  if (sr >= 0 && sr < r - 1) return;
   T* const Fv = a.F + (int64_t)vb * a.n;
   double* const Hv = a.H + (int64_t)vb * a.n;
   Slot* const slots = a.slots + (int64_t)vb * 3 * kSlots;
@@ -273,8 +277,19 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int wn = (int)min((int64_t)W, a.n - j0);
   const int tid = threadIdx.x;
 
-  // Loads that do not depend on the round's decisions are issued first: this
-  // window's fluid and, from round 1 on, its incoming segment counts/offsets.
+  // Every load that does not depend on this round's decisions is issued
+  // before the first wait: the stop flag, round r-1's sums, this window's
+  // fluid, its incoming record counts and the tables of its outgoing segments.
+  const int sr = ld_relaxed(&ctl->stop_round);
+  const Slot* P = slots + ((r + 2) % 3) * kSlots;  // set (r-1) % 3
+  double v[kSums] = {0, 0, 0, 0, 0, 0, 0};          // nf, snd, sd, ssc, nnz, taken, edges
+  double mrem = 0.0;
+  if (r >= 1 && tid < kSlots) {
+    const Slot p = P[tid];
+#pragma unroll
+    for (int f = 0; f < kSums; ++f) v[f] = p.sum[f];
+    mrem = __longlong_as_double((long long)p.mrem);
+  }
   constexpr int kWinPer = 4;  // window values prefetched per thread (the rest load later)
   T fv[kWinPer];
 #pragma unroll
@@ -283,26 +298,24 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     fv[k] = q < wn ? Fv[j0 + q] : (T)0;
   }
   const int was_active = a.active[(int64_t)vb * nb + b];
-  const int32_t* cnt_in = a.cnt[(r - 1) & 1] + vb * nb2 + (int64_t)b * nb;
-  int32_t c_own = 0, o_own = 0;  // first pass over sources (nb <= kRT in the common case)
-  if (r >= 1 && tid < nb) {
-    c_own = cnt_in[tid];
-    o_own = a.soff[(int64_t)b * nb + tid];
+  int32_t* const cnt_in = a.cnt[(r - 1) & 1] + vb * nb2 + (int64_t)b * nb;
+  int32_t c_own = 0, o_own = 0, cap_own = 0;  // first pass over windows (nb <= kRT usually)
+  int64_t base_own = 0;
+  if (tid < nb) {
+    if (r >= 1) {
+      c_own = cnt_in[tid];
+      o_own = a.soff[(int64_t)b * nb + tid];
+    }
+    base_own = a.bstart[tid] + a.soffT[(int64_t)b * nb + tid];
+    cap_own = a.capT[(int64_t)b * nb + tid];
   }
+  // Launch r itself records stop_round = r-1; an earlier stop ends this launch.
+  if (sr >= 0 && sr < r - 1) return;
 
   // 1. Decisions from round r-1's partial sums (identical in every workgroup).
   double theta = a.theta0;
   bool stop = mode == 1;
   if (r >= 1) {
-    const Slot* P = slots + ((r - 1) % 3) * kSlots;
-    double v[kSums] = {0, 0, 0, 0, 0, 0, 0};  // nf, snd, sd, ssc, nnz, taken, edges
-    double mrem = 0.0;
-    if (tid < kSlots) {
-      const Slot p = P[tid];
-#pragma unroll
-      for (int f = 0; f < kSums; ++f) v[f] = p.sum[f];
-      mrem = __longlong_as_double((long long)p.mrem);
-    }
     if (b == 0 && tid < kSlots) {  // set (r+1) % 3 is next used by launch r+1
       Slot* z = slots + ((r + 1) % 3) * kSlots + tid;
 #pragma unroll
@@ -347,26 +360,26 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     if (q < wn) win[q] = (double)fv[k];
   }
   for (int q = tid + kWinPer * kRT; q < wn; q += kRT) win[q] = (double)Fv[j0 + q];
-  long long total = 0;  // records addressed to this window in round r-1
-  if (r >= 1) {
-    if (tid < nb) {
-      s_pre[tid] = c_own;
-      s_soff[tid] = o_own;
-    }
-    for (int s = tid + kRT; s < nb; s += kRT) {
+  if (tid < nb) {
+    s_pre[tid] = c_own;
+    s_soff[tid] = o_own;
+    s_base[tid] = base_own;
+    s_cap[tid] = cap_own;
+  }
+  for (int s = tid + kRT; s < nb; s += kRT) {
+    if (r >= 1) {
       s_pre[s] = cnt_in[s];
       s_soff[s] = a.soff[(int64_t)b * nb + s];
+    } else {
+      s_pre[s] = 0;
     }
-    __syncthreads();
-    total = lds_exscan<kRT>(s_pre, nb, s_scr);
+    s_base[s] = a.bstart[s] + a.soffT[(int64_t)b * nb + s];
+    s_cap[s] = a.capT[(int64_t)b * nb + s];
   }
-  int32_t* cnt_out = a.cnt[r & 1] + vb * nb2;  // destination-major: these stores are posted
-  if (total == 0 && !was_active) {
-    // Nothing held and nothing arrived: the window sends nothing this round.
-    if (!stop)
-      for (int w = tid; w < nb; w += kRT) cnt_out[(int64_t)w * nb + b] = 0;
-    return;
-  }
+  __syncthreads();
+  long long total = 0;  // records addressed to this window in round r-1
+  if (r >= 1) total = lds_exscan<kRT>(s_pre, nb, s_scr);
+  if (total == 0 && !was_active) return;  // nothing held, nothing arrived: nothing to send
   if (total > 0) {
     const PairT<T>* pr = a.pairs[(r - 1) & 1] + (int64_t)vb * a.mrec;
     const int64_t base = a.bstart[b];
@@ -389,6 +402,8 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       for (int u = 0; u < kU; ++u)
         if (idx[u] >= 0 && e[u].loc < (uint32_t)wn) atomicAdd(&win[e[u].loc], (double)e[u].val);
     }
+    // The counts are consumed: clear the row for the launch that next writes it.
+    for (int s = tid; s < nb; s += kRT) cnt_in[s] = 0;
   }
   __syncthreads();
   if (stop) {
@@ -397,16 +412,13 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   }
 
   // 3. Take and expand, one tile of kRT nodes at a time.
-  for (int w = tid; w < nb; w += kRT) {
-    s_pre[w] = 0;  // now: records written per destination window
-    s_base[w] = a.bstart[w] + a.soffT[(int64_t)b * nb + w];
-    s_cap[w] = a.capT[(int64_t)b * nb + w];
-  }
+  for (int w = tid; w < nb; w += kRT) s_pre[w] = 0;  // now: records written per destination
   __syncthreads();
+  int32_t* const cnt_out = a.cnt[r & 1] + vb * nb2;  // destination-major, non-zero entries only
   PairT<T>* out = a.pairs[r & 1] + (int64_t)vb * a.mrec;
   const uint32_t wmask = (uint32_t)W - 1u;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // nf, snd, sd, ssc, nnz, taken, edges
-  double mrem = 0.0;
+  mrem = 0.0;  // now: the largest untaken score of this window
   for (int t0 = 0; t0 < wn; t0 += kSuper) {
     // A. Decide for kNPT nodes per thread, then issue all their loads at once.
     double f[kNPT];
@@ -514,7 +526,8 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     acc[6] += (double)etile;  // uniform: counted once below (thread 0 only)
     __syncthreads();
   }
-  for (int w = tid; w < nb; w += kRT) cnt_out[(int64_t)w * nb + b] = s_pre[w];
+  for (int w = tid; w < nb; w += kRT)
+    if (s_pre[w] > 0) cnt_out[(int64_t)w * nb + b] = min(s_pre[w], s_cap[w]);
   for (int q = tid; q < wn; q += kRT) Fv[j0 + q] = (T)win[q];
 
   // 4. This window's sums, added into its slot.
@@ -913,7 +926,18 @@ struct TuneParams {
   double c;
 };
 
-static TuneParams tune_params(const Graph* g, const di_tune* tn) {
+// Knobs of a call: the caller's tune, else what di_autotune cached for this
+// graph (mode DI_TUNE_SOLVE / DI_TUNE_BATCH, precision), else the defaults.
+static TuneParams tune_params(Graph* g, const di_tune* tn, int mode, int precision) {
+  di_tune cached;
+  if (!tn) {
+    std::lock_guard<std::mutex> lk(g->ws_mu);
+    const int pi = precision == DI_FP64 ? 1 : 0;
+    if (g->has_tuned[mode][pi]) {
+      cached = g->tuned[mode][pi];
+      tn = &cached;
+    }
+  }
   TuneParams p;
   p.sched = tn ? tn->schedule : DI_SCHED_MEAN;
   DI_REQUIRE(p.sched >= 0 && p.sched <= 2, "unknown schedule");
@@ -927,7 +951,7 @@ static TuneParams tune_params(const Graph* g, const di_tune* tn) {
 template <typename T>
 static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double* x,
                             di_stats* st, hipStream_t s) {
-  const TuneParams tp = tune_params(g, o->tune);
+  const TuneParams tp = tune_params(g, o->tune, DI_TUNE_SOLVE, o->precision);
   const bool dev = (o->flags & DI_DEVICE_PTRS) != 0;
   const bool resume = (o->flags & DI_RESUME) != 0;
   const int64_t max_rounds = o->max_rounds > 0 ? o->max_rounds : 1000000;
@@ -972,7 +996,7 @@ template <typename T>
 static di_status batch_impl(Graph* g, int32_t B, const int64_t* seed_ptr, const int32_t* seeds,
                             const double* seed_w, const di_opts* o, double* x, di_stats* st,
                             hipStream_t s) {
-  const TuneParams tp = tune_params(g, o->tune);
+  const TuneParams tp = tune_params(g, o->tune, DI_TUNE_BATCH, o->precision);
   const bool dev = (o->flags & DI_DEVICE_PTRS) != 0;
   const int64_t n = g->n;
   const int64_t max_rounds = o->max_rounds > 0 ? o->max_rounds : 1000000;
@@ -1149,7 +1173,7 @@ template <typename T>
 class SlotPoolT : public SlotPool {
  public:
   SlotPoolT(Graph* g, int precision, int capacity, const di_tune* tune) : g_(g), cap_(capacity) {
-    tp_ = tune_params(g, tune);
+    tp_ = tune_params(g, tune, DI_TUNE_BATCH, precision);
     ws_ = make_workspace(g, precision, tp_.wlog, capacity);
     round_.assign(capacity, 0);
     d_.assign(capacity, 0.85);

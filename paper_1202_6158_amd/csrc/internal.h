@@ -133,6 +133,9 @@ struct Graph {
   std::mutex ws_mu;
   std::vector<Workspace*> ws_free;
   int servers = 0;
+  // Autotuned knobs per (mode, precision), used by calls that pass no tune.
+  di_tune tuned[2][2] = {};
+  bool has_tuned[2][2] = {};
   ~Graph();
 };
 

@@ -46,6 +46,11 @@ class Tune(ctypes.Structure):
                 ("window_log2", ctypes.c_int32), ("check_every", ctypes.c_int32)]
 
 
+class TuneTrial(ctypes.Structure):
+    _fields_ = [("tune", Tune), ("seconds", ctypes.c_double), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("d", ctypes.c_double), ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("normalize", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
@@ -109,6 +114,8 @@ _SIGS = {
     "di_power_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_diffuse_round": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P],
     "di_solve_batch": [_P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _P],
+    "di_autotune": [_P, ctypes.c_int32, ctypes.POINTER(Opts), ctypes.c_int32, _P, _P,
+                    ctypes.POINTER(Tune), _P, ctypes.c_int32, _P, _P],
     "di_server_create": [ctypes.POINTER(ServerOpts), _P],
     "di_server_add_graph": [_P, _P, _P],
     "di_server_submit": [_P, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_double,
@@ -307,6 +314,38 @@ def solve_batch(graph: Graph, seed_ptr, seeds, seed_w=None, d=0.85, tol=1e-6, pr
                              ctypes.byref(o), _ptr(x), st, _stream(stream))
     _check(rc, allow=(ENOTCONV,) if allow_notconv else ())
     return x, [st[b].as_dict() for b in range(B)]
+
+
+TUNE_SOLVE = 0
+TUNE_BATCH = 1
+_SCHED_NAME = {v: k for k, v in SCHEDULE.items()}
+
+
+def tune_dict(t: Tune) -> dict:
+    return {"schedule": _SCHED_NAME.get(t.schedule, t.schedule), "c": float(t.c),
+            "window_log2": int(t.window_log2), "check_every": int(t.check_every)}
+
+
+def autotune(graph: Graph, mode="solve", d=0.85, tol=1e-8, precision="fp32", seed_ptr=None,
+             seeds=None, max_rounds=0, stream=None):
+    """di_autotune: times trial solves (mode "solve": uniform V; "batch": the
+    given seed sets) and caches the fastest knobs in the graph.  Returns
+    (best Tune, list of trial dicts)."""
+    m = {"solve": TUNE_SOLVE, "batch": TUNE_BATCH}[mode]
+    o = make_opts(d, tol, precision, True, max_rounds, None, 0)
+    B = 0
+    if m == TUNE_BATCH:
+        seed_ptr = np.ascontiguousarray(seed_ptr, dtype=np.int64)
+        seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        B = len(seed_ptr) - 1
+    best = Tune()
+    trials = (TuneTrial * 64)()
+    nt = ctypes.c_int32()
+    _check(_lib.di_autotune(graph.handle, m, ctypes.byref(o), B, _ptr(seed_ptr), _ptr(seeds),
+                            ctypes.byref(best), trials, 64, ctypes.byref(nt), _stream(stream)))
+    out = [dict(tune_dict(trials[k].tune), seconds=trials[k].seconds, status=trials[k].status)
+           for k in range(min(nt.value, 64))]
+    return best, out
 
 
 class Server:

@@ -85,3 +85,12 @@ def test_binding_has_no_fallback(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def test_autotune_rejects_missing_graph():
+    from paper_1202_6158_amd import di
+    o = di.make_opts(0.85, 1e-8, "fp32")
+    best = di.Tune()
+    rc = di._lib.di_autotune(None, di.TUNE_SOLVE, ctypes.byref(o), 0, None, None,
+                             ctypes.byref(best), None, 0, None, None)
+    assert rc == di.EINVAL and "graph" in di.last_error()
