@@ -176,6 +176,12 @@ def bench_ppr_batch(di, G, g, args):
     import numpy as np
     import workloads as wl
     ptr, seeds = wl.ppr_seed_sets(g.n, 256, 100, seed=4)
+    tune = None
+    if not args.no_autotune:  # tuned on a separate sample of 32 seed sets
+        sp, ss = wl.ppr_seed_sets(g.n, 32, 100, seed=40)
+        best, _ = di.autotune(G, "batch", d=args.d, tol=1e-6, precision="fp32", seed_ptr=sp,
+                              seeds=ss)
+        tune = di.tune_dict(best)
     try:
         run = lambda: di.solve_batch(G, ptr, seeds, d=args.d, tol=1e-6, precision="fp32")
         t, outs = time_steps(run, 1, 1)
@@ -190,7 +196,7 @@ def bench_ppr_batch(di, G, g, args):
     import torch
     torch.cuda.synchronize()
     solo = (time.perf_counter() - t1) / 16
-    return {"vectors": 256, "tol": 1e-6, "seconds": t, "vectors_per_s": 256 / t,
+    return {"vectors": 256, "tol": 1e-6, "tune": tune, "seconds": t, "vectors_per_s": 256 / t,
             "solo_seconds_per_vector": solo, "speedup_vs_solo": solo * 256 / t,
             "edges_diffused": int(sum(s["edges_diffused"] for s in stats))}
 
@@ -238,6 +244,17 @@ def bench_serve(di, args):
     import workloads as wl
     graphs = [wl.recipe(r) for r in SERVE_GRAPHS]
     G = [di.Graph(g) for g in graphs]
+    tunes = {}
+    if not args.no_autotune:  # per graph, on 16 seed sets drawn like the stream's
+        for name, g, x in zip(SERVE_GRAPHS, graphs, G):
+            rng = np.random.default_rng(7)
+            sz = np.clip(np.floor(np.exp(rng.uniform(0, np.log(1001), 16))), 1, 1000).astype(int)
+            sets = [wl.request_seeds(g.n, int(k), int(rng.integers(1 << 62))) for k in sz]
+            ptr = np.concatenate([[0], np.cumsum([len(q) for q in sets])]).astype(np.int64)
+            best, _ = di.autotune(x, "batch", d=args.d, tol=1e-6, precision="fp32", seed_ptr=ptr,
+                                  seeds=np.concatenate(sets))
+            tunes[name] = di.tune_dict(best)
+            log("serve autotune %s: %s" % (name, tunes[name]))
     srv = di.Server(hbm_budget_bytes=args.serve_hbm_gib << 30, max_slots=256, topk=100)
     gids = [srv.add_graph(x) for x in G]
     caps = srv.stats()["hbm_in_use"]
@@ -294,7 +311,7 @@ def bench_serve(di, args):
     solo_qps = ns / solo_s
     return {
         "graphs": {n: {"n": g.n, "links": g.m} for n, g in zip(SERVE_GRAPHS, graphs)},
-        "hbm_budget_gib": args.serve_hbm_gib, "slot_bytes_total": caps,
+        "hbm_budget_gib": args.serve_hbm_gib, "slot_bytes_total": caps, "tune": tunes,
         "stream": {"rate_per_s": args.serve_rate, "warmup_s": args.serve_warmup,
                    "measured_s": args.serve_seconds, "requests": len(res),
                    "measured_requests": len(meas), "ok": ok,
@@ -325,6 +342,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ppr", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="library default knobs instead of di_autotune's choice")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
@@ -360,6 +379,19 @@ def main():
     g = wl.recipe(args.workload)
     G = di.Graph(g)
     log("graph n=%d links=%d dangling=%d" % (g.n, g.m, g.n_dangling))
+
+    # ---- autotuner: the knobs every later solve on this graph uses
+    tune_info = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        best, trials = di.autotune(G, "solve", d=args.d, tol=args.tol, precision=args.precision)
+        ok = [t for t in trials if t["status"] == 0]
+        tune_info = {"best": di.tune_dict(best), "candidates": len(trials),
+                     "default_ms": 1e3 * trials[0]["seconds"],
+                     "best_ms": 1e3 * min(t["seconds"] for t in ok),
+                     "tuning_s": time.perf_counter() - t0}
+        log("autotune: %s (%.3f ms vs %.3f ms default)" % (tune_info["best"], tune_info["best_ms"],
+                                                          tune_info["default_ms"]))
 
     # ---- D-iteration (the measured step): K un-instrumented solves give the
     # throughput; the same K solves again with per-launch HIP events (the
@@ -411,6 +443,7 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "links": g.m, "dangling": g.n_dangling,
                    "d": args.d, "tol": args.tol, "V": "uniform",
                    "recipe": wl.RECIPES.get(args.workload)},
+        "tune": tune_info,
         "time_to_residual_ms": sec * 1e3,
         "device_ms_per_solve": dev_ms,
         "ms_per_solve_with_launch_events": sec_timed * 1e3,

@@ -201,9 +201,12 @@ typedef struct di_tune_trial {
  * OP / OP2 scores), the threshold factor c and the window size of the binned
  * scatter for this graph by timing trial solves on the device: first every
  * schedule x c in {0.25, 0.5, 1, 2, 4} at the default window, then the best
- * pair at the neighbouring window sizes.  Any schedule converges to the same
- * limit (the order independence of Section 2), so only speed is compared;
- * candidates that do not converge within opts->max_rounds are discarded.
+ * pair at larger and smaller windows, one size at a time in each direction
+ * while the time improves.  Any schedule converges to the same
+ * limit (the order independence of Section 2), so only speed is compared.
+ * The default knobs (mean, c = 1) run first; every other candidate gets at
+ * most four times their rounds (at least 64, at most opts->max_rounds when
+ * set) and is discarded if it does not converge within them.
  *
  * mode DI_TUNE_SOLVE times di_solve with uniform V and opts (d, tol,
  * precision).  DI_TUNE_BATCH times di_solve_batch on the B seed sets given

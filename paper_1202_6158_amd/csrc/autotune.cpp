@@ -25,6 +25,7 @@ struct Trial {
   di_tune tune;
   double seconds;
   di_status status;
+  int64_t rounds;  // most rounds any vector took
 };
 
 // Seconds per solve (per vector for batches) of one candidate: one untimed
@@ -32,7 +33,7 @@ struct Trial {
 Trial run_candidate(const di_graph* g, int mode, const di_opts& base, int32_t B,
                     const int64_t* seed_ptr, const int32_t* seeds, const di_tune& t,
                     hipStream_t s) {
-  Trial out{t, std::numeric_limits<double>::infinity(), DI_OK};
+  Trial out{t, std::numeric_limits<double>::infinity(), DI_OK, 0};
   di_opts o = base;
   o.tune = &t;
   o.flags = 0;
@@ -47,6 +48,7 @@ Trial run_candidate(const di_graph* g, int mode, const di_opts& base, int32_t B,
       out.status = rc;
       return out;
     }
+    for (const di_stats& x : st) out.rounds = std::max(out.rounds, x.rounds);
     if (rep == 0) continue;
     // a batch reports the time of its whole group on every vector
     const double secs = mode == DI_TUNE_BATCH ? st[0].seconds / B : st[0].seconds;
@@ -77,40 +79,52 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
     DI_REQUIRE(w0 > 0, "graph has too many nodes for the window tables");
 
     std::vector<Trial> done;
+    di_opts cand_opts = *opts;
     auto run = [&](int sched, float c, int wlog) {
       di_tune t{};
       t.schedule = sched;
       t.c = c;
       t.window_log2 = wlog;
       t.check_every = 0;
-      done.push_back(run_candidate(g, mode, *opts, B, seed_ptr, seeds, t, s));
+      done.push_back(run_candidate(g, mode, cand_opts, B, seed_ptr, seeds, t, s));
       return done.back();
     };
     auto better = [](const Trial& a, const Trial& b) {
       if ((a.status == DI_OK) != (b.status == DI_OK)) return a.status == DI_OK;
       return a.seconds < b.seconds;
     };
+    // 0. the default knobs set the round budget of the other candidates: a
+    //    threshold too high for the graph takes few nodes per round and may
+    //    need orders of magnitude more rounds; such a candidate is cut off
+    //    at four times the default's rounds and discarded.
+    Trial win = run(DI_SCHED_MEAN, 1.0f, w0);
+    if (win.status == DI_OK) {
+      const int64_t cap = std::max<int64_t>(64, 4 * win.rounds);
+      cand_opts.max_rounds = opts->max_rounds > 0 ? std::min(opts->max_rounds, cap) : cap;
+    }
     // 1. schedule x threshold factor at the default window
     const int scheds[] = {DI_SCHED_MEAN, DI_SCHED_OP2, DI_SCHED_OP};
     const float cs[] = {0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
-    Trial win{};
-    win.status = DI_ENOTCONV;
-    win.seconds = std::numeric_limits<double>::infinity();
     for (int sc : scheds)
       for (float c : cs) {
+        if (sc == DI_SCHED_MEAN && c == 1.0f) continue;  // step 0
         const Trial t = run(sc, c, w0);
         if (better(t, win)) win = t;
       }
-    // 2. neighbouring window sizes for the best pair (sizes the LDS budget or
-    //    the window-count limit clamp to an already tried size are skipped)
+    // 2. window size for the best pair: walk from the default in each
+    //    direction while the time improves (sizes that the LDS budget or the
+    //    window-count limit clamp to an already tried size end the walk)
     if (win.status == DI_OK) {
       std::vector<int> tried{w0};
-      for (int dw : {-1, 1}) {
-        const int wl = window_log2_for(g->n, w0 + dw);
-        if (wl <= 0 || std::find(tried.begin(), tried.end(), wl) != tried.end()) continue;
-        tried.push_back(wl);
-        const Trial t = run(win.tune.schedule, win.tune.c, wl);
-        if (better(t, win)) win = t;
+      for (int dir : {-1, 1}) {
+        for (int wl = w0 + dir;; wl += dir) {
+          const int eff = window_log2_for(g->n, wl);
+          if (eff <= 0 || std::find(tried.begin(), tried.end(), eff) != tried.end()) break;
+          tried.push_back(eff);
+          const Trial t = run(win.tune.schedule, win.tune.c, eff);
+          if (!better(t, win)) break;
+          win = t;
+        }
       }
     }
     const int nt = (int)done.size();
