@@ -274,9 +274,13 @@ def bench_serve(di, args):
         lg = np.array([r["t_done"] - r["t_submit"] for r, tk, q in zip(res, t, gi)
                        if tk >= args.serve_warmup and q == g])
         if len(lg):
+            rg = [r for r, q in zip(res, gi) if q == g]
             per_graph[SERVE_GRAPHS[g]] = {"requests": int(len(lg)),
                                           "p50_ms": 1e3 * float(np.percentile(lg, 50)),
-                                          "p99_ms": 1e3 * float(np.percentile(lg, 99))}
+                                          "p99_ms": 1e3 * float(np.percentile(lg, 99)),
+                                          "mean_rounds": float(np.mean([r["rounds"] for r in rg])),
+                                          "mean_links": float(np.mean([r["edges_diffused"]
+                                                                       for r in rg]))}
     srv.close()
 
     # capacity: a burst of requests with the stream's mix, all submitted at once

@@ -241,7 +241,7 @@ __device__ __forceinline__ int upper_idx(const I* a, int n, long long x) {
 
 constexpr int kRT = kRoundThreads;  // threads per round workgroup
 constexpr int kU = 4;               // independent memory operations per thread per step
-constexpr int kSuper = 2048;        // window nodes decided and expanded per pass
+constexpr int kSuper = 1024;        // window nodes decided and expanded per pass
 constexpr int kNPT = kSuper / kRT;  // nodes per thread per pass
 
 // One round; mode 1 forces a fold-only launch (after an explicit single round).
@@ -789,18 +789,19 @@ static int grid_for(int64_t n, int cap) {
 template <typename T, int SCHED>
 static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, LaunchTimer* lt) {
   const size_t smem = round_lds_bytes(a.wlog, a.nb);
-  static size_t dyn_limit = 0;
-  if (dyn_limit == 0) {
-    // Dynamic LDS may use what the static part leaves of the workgroup limit.
+  // Dynamic LDS may use what the static part leaves of the workgroup limit
+  // (set once per kernel instance; thread-safe initialisation).
+  static const size_t dyn_limit = [] {
     hipFuncAttributes fa;
     DI_HIP(hipFuncGetAttributes(&fa, (const void*)k_round<T, SCHED>));
     int dev = 0, lim = 0;
     DI_HIP(hipGetDevice(&dev));
     DI_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    dyn_limit = (size_t)lim - fa.sharedSizeBytes;
+    const size_t dl = (size_t)lim - fa.sharedSizeBytes;
     DI_HIP(hipFuncSetAttribute((const void*)k_round<T, SCHED>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_limit));
-  }
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl));
+    return dl;
+  }();
   DI_REQUIRE(smem <= dyn_limit, "window tables exceed the LDS available to the round kernel");
   const dim3 grid(a.nb, a.nvec);
   if (lt && lt->on) {

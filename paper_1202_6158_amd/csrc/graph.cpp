@@ -29,7 +29,7 @@ size_t round_lds_bytes(int wlog, int nb) {
 }
 
 int window_log2_for(int64_t n, int requested) {
-  constexpr size_t kLdsBudget = 116 * 1024;  // 160 KiB minus the round kernel's static LDS
+  constexpr size_t kLdsBudget = 136 * 1024;  // 160 KiB minus the round kernel's static LDS (21 KiB)
   int k = 8;
   if (requested >= 8) {
     k = std::min(requested, 14);

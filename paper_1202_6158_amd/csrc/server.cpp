@@ -1,13 +1,15 @@
 // Continuous-batching personalised PageRank server.
 //
-// Requests (a seed set, d, tol) are queued per graph.  A scheduler thread
-// repeats one engine step: admit queued requests into free slots of the
-// graph's slot pool (device state sized from the HBM budget), run one
-// D-iteration round for every active slot of every graph (slots admitted at
-// different times sit at different rounds of their own solves and share each
-// launch), detect the slots whose solve stopped, flush them, take their top-k
-// on the device and complete the requests.  Work of requests that arrive while
-// others run overlaps with theirs from the next step on.
+// Requests (a seed set, d, tol) are queued per graph.  Every graph has an
+// engine thread and a HIP stream of its own; the thread repeats one engine
+// step: admit queued requests into free slots of the graph's slot pool
+// (device state sized from the HBM budget), run one D-iteration round for
+// every active slot (slots admitted at different times sit at different rounds
+// of their own solves and share each launch), detect the slots whose solve
+// stopped, flush them, take their top-k on the device and complete the
+// requests.  Work of requests that arrive while others run overlaps with
+// theirs from the next step on, and the graphs' launches overlap on the
+// device, so a small graph's requests never wait for a large graph's rounds.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -41,6 +43,8 @@ struct Request {
 
 struct GraphEntry {
   Graph* g = nullptr;
+  hipStream_t stream = nullptr;
+  std::thread th;
   std::unique_ptr<SlotPool> pool;
   std::deque<Request*> queue;
   std::vector<Request*> slot_req;  // per slot: the request it runs (or NULL)
@@ -54,14 +58,13 @@ struct Server {
   di_tune tune;
   bool has_tune = false;
   int device = 0;
-  hipStream_t stream = nullptr;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::vector<GraphEntry> graphs;
   std::unordered_map<uint64_t, Request*> reqs;
   uint64_t next_id = 1;
   bool stop = false;
-  std::thread th;
+  bool started = false;  // engine threads run (no graphs may be added)
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   int64_t submitted = 0, admitted = 0, completed = 0, cancelled = 0;
   int64_t hbm_in_use = 0;
@@ -69,15 +72,15 @@ struct Server {
   double t_first = -1, t_last = 0;
   std::string thread_error;
   bool log = false;  // DI_LOG=1: one line per engine step on stderr
-  int64_t steps = 0;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
-  void loop();
+  void loop(int gi);
 };
 
-void Server::loop() {
+// Engine thread of graph gi.
+void Server::loop(int gi) {
   if (hipSetDevice(device) != hipSuccess) {
     std::lock_guard<std::mutex> lk(mu);
     thread_error = "scheduler could not select the device";
@@ -85,133 +88,119 @@ void Server::loop() {
     cv_done.notify_all();
     return;
   }
+  GraphEntry& ge = graphs[gi];
+  int64_t step_no = 0;
   for (;;) {
-    std::vector<std::vector<SlotInit>> inits(graphs.size());
-    std::vector<std::vector<int>> active(graphs.size());
+    std::vector<SlotInit> inits;
+    std::vector<int> active;
     {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] {
-        if (stop) return true;
-        for (auto& ge : graphs)
-          if (!ge.queue.empty() || (int)ge.free_slots.size() < ge.pool->capacity()) return true;
-        return false;
+        return stop || !ge.queue.empty() || (int)ge.free_slots.size() < ge.pool->capacity();
       });
       if (stop) return;
       const double t = now();
-      for (size_t gi = 0; gi < graphs.size(); ++gi) {
-        GraphEntry& ge = graphs[gi];
-        // cancelled running requests release their slots
-        for (int q = 0; q < (int)ge.slot_req.size(); ++q) {
-          Request* r = ge.slot_req[q];
-          if (r && r->cancel) {
-            r->res.status = DI_ECANCELED;
-            r->t_done = t;
-            r->done = true;
-            ++cancelled;
-            ge.slot_req[q] = nullptr;
-            ge.free_slots.push_back(q);
-          }
+      // cancelled running requests release their slots
+      for (int q = 0; q < (int)ge.slot_req.size(); ++q) {
+        Request* r = ge.slot_req[q];
+        if (r && r->cancel) {
+          r->res.status = DI_ECANCELED;
+          r->t_done = t;
+          r->done = true;
+          ++cancelled;
+          ge.slot_req[q] = nullptr;
+          ge.free_slots.push_back(q);
         }
-        // admission: FIFO into free slots
-        while (!ge.queue.empty() && !ge.free_slots.empty()) {
-          Request* r = ge.queue.front();
-          ge.queue.pop_front();
-          if (r->cancel) {
-            r->res.status = DI_ECANCELED;
-            r->t_done = t;
-            r->done = true;
-            ++cancelled;
-            continue;
-          }
-          const int slot = ge.free_slots.back();
-          ge.free_slots.pop_back();
-          r->slot = slot;
-          r->t_admit = t;
-          ge.slot_req[slot] = r;
-          ++admitted;
-          SlotInit in;
-          in.slot = slot;
-          in.d = r->d;
-          in.tol = r->tol;
-          in.seeds = r->seeds;
-          in.w = r->w;
-          inits[gi].push_back(std::move(in));
-        }
-        for (int q = 0; q < (int)ge.slot_req.size(); ++q)
-          if (ge.slot_req[q]) active[gi].push_back(q);
       }
+      // admission: FIFO into free slots
+      while (!ge.queue.empty() && !ge.free_slots.empty()) {
+        Request* r = ge.queue.front();
+        ge.queue.pop_front();
+        if (r->cancel) {
+          r->res.status = DI_ECANCELED;
+          r->t_done = t;
+          r->done = true;
+          ++cancelled;
+          continue;
+        }
+        const int slot = ge.free_slots.back();
+        ge.free_slots.pop_back();
+        r->slot = slot;
+        r->t_admit = t;
+        ge.slot_req[slot] = r;
+        ++admitted;
+        SlotInit in;
+        in.slot = slot;
+        in.d = r->d;
+        in.tol = r->tol;
+        in.seeds = r->seeds;
+        in.w = r->w;
+        inits.push_back(std::move(in));
+      }
+      for (int q = 0; q < (int)ge.slot_req.size(); ++q)
+        if (ge.slot_req[q]) active.push_back(q);
       cv_done.notify_all();
     }
-    std::vector<std::vector<SlotResult>> results(graphs.size());
+    std::vector<SlotResult> results;
     if (log) {
-      size_t na = 0, ni = 0;
-      for (size_t gi = 0; gi < graphs.size(); ++gi) {
-        na += active[gi].size();
-        ni += inits[gi].size();
-      }
-      fprintf(stderr, "[di server] step %lld t=%.4f admit %zu active %zu\n", (long long)steps,
-              now(), ni, na);
+      fprintf(stderr, "[di server] graph %d step %lld t=%.4f admit %zu active %zu\n", gi,
+              (long long)step_no, now(), inits.size(), active.size());
       fflush(stderr);
     }
-    ++steps;
+    ++step_no;
     di_status rc = guarded([&] {
-      for (size_t gi = 0; gi < graphs.size(); ++gi) graphs[gi].pool->admit(inits[gi], stream);
-      for (size_t gi = 0; gi < graphs.size(); ++gi) graphs[gi].pool->step(active[gi], stream);
-      for (size_t gi = 0; gi < graphs.size(); ++gi) {
-        if (active[gi].empty()) continue;
-        const std::vector<int> fin = graphs[gi].pool->stopped(active[gi], stream);
-        graphs[gi].pool->finish(fin, opts.topk, results[gi], stream);
+      ge.pool->admit(inits, ge.stream);
+      ge.pool->step(active, ge.stream);
+      if (!active.empty()) {
+        const std::vector<int> fin = ge.pool->stopped(active, ge.stream);
+        ge.pool->finish(fin, opts.topk, results, ge.stream);
       }
     });
     std::lock_guard<std::mutex> lk(mu);
     if (rc != DI_OK) {
       thread_error = last_error_ref();
-      // fail every running request; the server keeps its queue
+      // fail every running request of this graph; its queue stays
       const double t = now();
-      for (auto& ge : graphs)
-        for (int q = 0; q < (int)ge.slot_req.size(); ++q)
-          if (Request* r = ge.slot_req[q]) {
-            r->res.status = DI_EDEVICE;
-            r->t_done = t;
-            r->done = true;
-            ge.slot_req[q] = nullptr;
-            ge.free_slots.push_back(q);
-          }
+      for (int q = 0; q < (int)ge.slot_req.size(); ++q)
+        if (Request* r = ge.slot_req[q]) {
+          r->res.status = DI_EDEVICE;
+          r->t_done = t;
+          r->done = true;
+          ge.slot_req[q] = nullptr;
+          ge.free_slots.push_back(q);
+        }
       cv_done.notify_all();
       continue;
     }
     const double t = now();
-    for (size_t gi = 0; gi < graphs.size(); ++gi) {
-      GraphEntry& ge = graphs[gi];
-      for (const SlotResult& sr : results[gi]) {
-        Request* r = ge.slot_req[sr.slot];
-        ge.slot_req[sr.slot] = nullptr;
-        ge.free_slots.push_back(sr.slot);
-        if (!r) continue;
-        di_result& o = r->res;
-        o.req_id = r->id;
-        o.status = r->cancel ? DI_ECANCELED : sr.status;
-        o.k = (int32_t)std::min<size_t>(sr.ids.size(), 1024);
-        for (int k = 0; k < o.k; ++k) {
-          o.top_ids[k] = sr.ids[k];
-          o.top_x[k] = sr.x[k];
-        }
-        o.residual_l1 = sr.residual;
-        o.err_bound_l1 = sr.bound;
-        o.rounds = sr.rounds;
-        o.edges_diffused = sr.edges;
-        r->t_done = t;
-        o.t_submit = r->t_submit;
-        o.t_admit = r->t_admit;
-        o.t_done = t;
-        r->done = true;
-        if (r->cancel) {
-          ++cancelled;
-        } else {
-          ++completed;
-          latencies.push_back(t - r->t_submit);
-          t_last = t;
-        }
+    for (const SlotResult& sr : results) {
+      Request* r = ge.slot_req[sr.slot];
+      ge.slot_req[sr.slot] = nullptr;
+      ge.free_slots.push_back(sr.slot);
+      if (!r) continue;
+      di_result& o = r->res;
+      o.req_id = r->id;
+      o.status = r->cancel ? DI_ECANCELED : sr.status;
+      o.k = (int32_t)std::min<size_t>(sr.ids.size(), 1024);
+      for (int k = 0; k < o.k; ++k) {
+        o.top_ids[k] = sr.ids[k];
+        o.top_x[k] = sr.x[k];
+      }
+      o.residual_l1 = sr.residual;
+      o.err_bound_l1 = sr.bound;
+      o.rounds = sr.rounds;
+      o.edges_diffused = sr.edges;
+      r->t_done = t;
+      o.t_submit = r->t_submit;
+      o.t_admit = r->t_admit;
+      o.t_done = t;
+      r->done = true;
+      if (r->cancel) {
+        ++cancelled;
+      } else {
+        ++completed;
+        latencies.push_back(t - r->t_submit);
+        t_last = std::max(t_last, t);
       }
     }
     cv_done.notify_all();
@@ -259,7 +248,6 @@ di_status di_server_create(const di_server_opts* opts, di_server** out) {
       }
       s->opts.tune = nullptr;
       DI_HIP(hipGetDevice(&s->device));
-      DI_HIP(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
       const char* lg = getenv("DI_LOG");
       s->log = lg && lg[0] == '1';
     } catch (...) {
@@ -274,7 +262,7 @@ di_status di_server_add_graph(di_server* s, const di_graph* g, int32_t* graph_id
   return guarded([&] {
     DI_REQUIRE(s && g && graph_id, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
-    DI_REQUIRE(!s->th.joinable(), "graphs must be added before the first submit");
+    DI_REQUIRE(!s->started, "graphs must be added before the first submit");
     Graph* gg = const_cast<di_graph*>(g);
     // Slots per graph: an equal share of the budget among up to 4 graphs.
     const int64_t per = slot_bytes(gg, s->opts.precision);
@@ -288,6 +276,7 @@ di_status di_server_add_graph(di_server* s, const di_graph* g, int32_t* graph_id
     GraphEntry ge;
     ge.g = gg;
     ge.pool.reset(make_slot_pool(gg, s->opts.precision, cap, s->has_tune ? &s->tune : nullptr));
+    DI_HIP(hipStreamCreateWithFlags(&ge.stream, hipStreamNonBlocking));
     ge.slot_req.assign(cap, nullptr);
     for (int q = cap - 1; q >= 0; --q) ge.free_slots.push_back(q);
     s->hbm_in_use += ge.pool->bytes();
@@ -338,8 +327,12 @@ di_status di_server_submit(di_server* s, int32_t graph_id, int32_t n_seeds, cons
     s->graphs[graph_id].queue.push_back(r);
     ++s->submitted;
     *req_id = r->id;
-    if (!s->th.joinable()) s->th = std::thread([s] { s->loop(); });
-    s->cv_work.notify_one();
+    if (!s->started) {
+      s->started = true;
+      for (int gi = 0; gi < (int)s->graphs.size(); ++gi)
+        s->graphs[gi].th = std::thread([s, gi] { s->loop(gi); });
+    }
+    s->cv_work.notify_all();
   });
 }
 
@@ -385,7 +378,7 @@ di_status di_server_cancel(di_server* s, uint64_t req_id) {
     auto it = s->reqs.find(req_id);
     DI_REQUIRE(it != s->reqs.end(), "unknown request id");
     it->second->cancel = true;
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();
   });
 }
 
@@ -427,12 +420,16 @@ di_status di_server_destroy(di_server* s) {
       s->stop = true;
       s->cv_work.notify_all();
     }
-    if (s->th.joinable()) s->th.join();
-    (void)hipStreamSynchronize(s->stream);
+    for (auto& ge : s->graphs)
+      if (ge.th.joinable()) ge.th.join();
+    for (auto& ge : s->graphs) (void)hipStreamSynchronize(ge.stream);
     for (auto& kv : s->reqs) delete kv.second;
-    for (auto& ge : s->graphs) ge.g->servers -= 1;
+    for (auto& ge : s->graphs) {
+      ge.g->servers -= 1;
+      ge.pool.reset();
+      (void)hipStreamDestroy(ge.stream);
+    }
     s->graphs.clear();
-    (void)hipStreamDestroy(s->stream);
     delete s;
   });
 }
