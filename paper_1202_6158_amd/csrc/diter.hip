@@ -239,8 +239,22 @@ __device__ __forceinline__ int upper_idx(const I* a, int n, long long x) {
   return lo;
 }
 
+// Workgroups go to the 8 XCDs round-robin by linear id.  The round kernel
+// maps linear ids to (vector column, window) so that each XCD gets a
+// contiguous range of windows: neighbouring windows then share an L2, where
+// their writes into the same lines of the count matrix and of the record
+// regions can merge.  A bijection of [0, nb * columns).
+__device__ __forceinline__ void xcd_window(int nb, int* col, int* win) {
+  const long long total = (long long)nb * gridDim.y;
+  const long long L = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+  const long long x = L & 7, k = L >> 3, base = total >> 3, rem = total & 7;
+  const long long m = x * base + (x < rem ? x : rem) + k;
+  *col = (int)(m / nb);
+  *win = (int)(m - (long long)(*col) * nb);
+}
+
 constexpr int kRT = kRoundThreads;  // threads per round workgroup
-constexpr int kU = 4;               // independent memory operations per thread per step
+constexpr int kRun = 4;             // consecutive records / links per thread per step
 constexpr int kSuper = 1024;        // window nodes decided and expanded per pass
 constexpr int kNPT = kSuper / kRT;  // nodes per thread per pass
 
@@ -248,7 +262,9 @@ constexpr int kNPT = kSuper / kRT;  // nodes per thread per pass
 template <typename T, int SCHED>
 __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_round(DiArgs<T> a, int r,
                                                                                    int mode) {
-  const int vb = a.vmap ? a.vmap[blockIdx.y] : blockIdx.y;  // vector (0 for a single solve)
+  int ycol, b;  // vector column of the launch, window
+  xcd_window(a.nb, &ycol, &b);
+  const int vb = a.vmap ? a.vmap[ycol] : ycol;  // vector (0 for a single solve)
   if (a.vround) r = a.vround[vb];
   const double d = a.vd ? a.vd[vb] : a.d;
   const double tol = a.vtol ? a.vtol[vb] : a.tol;
@@ -272,7 +288,6 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   __shared__ double s_red[8 * (kRT / 64)];
   __shared__ long long s_scr[2 * (kRT / 64)];
 
-  const int b = blockIdx.x;
   const int64_t j0 = (int64_t)b << a.wlog;
   const int wn = (int)min((int64_t)W, a.n - j0);
   const int tid = threadIdx.x;
@@ -383,23 +398,32 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   if (total > 0) {
     const PairT<T>* pr = a.pairs[(r - 1) & 1] + (int64_t)vb * a.mrec;
     const int64_t base = a.bstart[b];
-    for (long long i0 = tid; i0 < total; i0 += kU * kRT) {
-      int64_t idx[kU];
+    // Each thread takes kRun consecutive records: one search for the segment
+    // of the first, then a forward walk over the segment boundaries.
+    for (long long i0 = (long long)tid * kRun; i0 < total; i0 += (long long)kRT * kRun) {
+      int s = upper_idx(s_pre, nb, i0);
+      long long nxt = s + 1 < nb ? s_pre[s + 1] : total;
+      int64_t sb = base + s_soff[s] - s_pre[s];  // record index = sb + i within segment s
+      int64_t idx[kRun];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const long long i = i0 + (long long)u * kRT;
+      for (int u = 0; u < kRun; ++u) {
+        const long long i = i0 + u;
         idx[u] = -1;
         if (i < total) {
-          const int s = upper_idx(s_pre, nb, i);
-          idx[u] = base + s_soff[s] + (i - s_pre[s]);
+          while (i >= nxt) {
+            ++s;
+            nxt = s + 1 < nb ? s_pre[s + 1] : total;
+            sb = base + s_soff[s] - s_pre[s];
+          }
+          idx[u] = sb + i;
         }
       }
-      PairT<T> e[kU];
+      PairT<T> e[kRun];
 #pragma unroll
-      for (int u = 0; u < kU; ++u)
+      for (int u = 0; u < kRun; ++u)
         if (idx[u] >= 0) e[u] = pr[idx[u]];
 #pragma unroll
-      for (int u = 0; u < kU; ++u)
+      for (int u = 0; u < kRun; ++u)
         if (idx[u] >= 0 && e[u].loc < (uint32_t)wn) atomicAdd(&win[e[u].loc], (double)e[u].val);
     }
     // The counts are consumed: clear the row for the launch that next writes it.
@@ -484,31 +508,40 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       eoff += dg;
     }
     __syncthreads();
-    // C. Push every staged link: kU independent link reads per thread per step.
+    // C. Push every staged link: each thread takes kRun consecutive links,
+    //    one search for the node of the first, then a forward walk.
     const int bcount = (int)ntile;
-    for (long long t00 = tid; t00 < etile; t00 += kU * kRT) {
-      int64_t e[kU];
-      int kk[kU];
+    for (long long t00 = (long long)tid * kRun; t00 < etile; t00 += (long long)kRT * kRun) {
+      int k = upper_idx(s_beo, bcount, t00);
+      long long nxt = k + 1 < bcount ? s_beo[k + 1] : etile;
+      int64_t lb = s_brow[k] - s_beo[k];  // link index = lb + t for node k
+      double sh = s_bsh[k];
+      int64_t e[kRun];
+      double v[kRun];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const long long t = t00 + (long long)u * kRT;
+      for (int u = 0; u < kRun; ++u) {
+        const long long t = t00 + u;
         e[u] = -1;
         if (t < etile) {
-          kk[u] = upper_idx(s_beo, bcount, t);
-          e[u] = s_brow[kk[u]] + (t - s_beo[kk[u]]);
+          while (t >= nxt) {
+            ++k;
+            nxt = k + 1 < bcount ? s_beo[k + 1] : etile;
+            lb = s_brow[k] - s_beo[k];
+            sh = s_bsh[k];
+          }
+          e[u] = lb + t;
+          v[u] = sh;
         }
       }
-      uint32_t dst[kU];
-      double v[kU];
+      uint32_t dst[kRun];
 #pragma unroll
-      for (int u = 0; u < kU; ++u)
+      for (int u = 0; u < kRun; ++u)
         if (e[u] >= 0) {
           dst[u] = (uint32_t)a.col[e[u]];
-          v[u] = s_bsh[kk[u]];
           if (a.weighted) v[u] *= a.w[e[u]];
         }
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+      for (int u = 0; u < kRun; ++u) {
         if (e[u] < 0) continue;
         const int w = (int)(dst[u] >> a.wlog);
         const int rank = atomicAdd(&s_pre[w], 1);
