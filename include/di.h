@@ -84,6 +84,7 @@ typedef struct di_tune {
   float c;             /* threshold factor (default 1.0) */
   int32_t window_log2; /* destination window of the binned scatter: 2^k nodes (8..14) */
   int32_t check_every; /* rounds between host checks of the device done flag (0 = adaptive) */
+  int32_t threads;     /* round workgroup size: 512 (default, 0) or 1024 (more loads in flight) */
 } di_tune;
 
 typedef struct di_opts {
@@ -202,7 +203,7 @@ typedef struct di_tune_trial {
  * scatter for this graph by timing trial solves on the device: first every
  * schedule x c in {0.25, 0.5, 1, 2, 4} at the default window, then the best
  * pair at larger and smaller windows, one size at a time in each direction
- * while the time improves.  Any schedule converges to the same
+ * while the time improves, then the winner with 1024-thread workgroups.  Any schedule converges to the same
  * limit (the order independence of Section 2), so only speed is compared.
  * The default knobs (mean, c = 1) run first; every other candidate gets at
  * most four times their rounds (at least 64, at most opts->max_rounds when

@@ -80,12 +80,13 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
 
     std::vector<Trial> done;
     di_opts cand_opts = *opts;
-    auto run = [&](int sched, float c, int wlog) {
+    auto run = [&](int sched, float c, int wlog, int threads = 0) {
       di_tune t{};
       t.schedule = sched;
       t.c = c;
       t.window_log2 = wlog;
       t.check_every = 0;
+      t.threads = threads;
       done.push_back(run_candidate(g, mode, cand_opts, B, seed_ptr, seeds, t, s));
       return done.back();
     };
@@ -126,6 +127,11 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
           win = t;
         }
       }
+    }
+    // 3. the winner with 1024-thread workgroups
+    if (win.status == DI_OK) {
+      const Trial t = run(win.tune.schedule, win.tune.c, win.tune.window_log2, 1024);
+      if (better(t, win)) win = t;
     }
     const int nt = (int)done.size();
     for (int k = 0; k < nt && k < max_trials; ++k) {

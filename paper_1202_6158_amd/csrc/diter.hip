@@ -78,6 +78,7 @@ struct DiArgs {
   double d, tol, c, theta0;
   int64_t max_rounds;
   int weighted;
+  int threads;  // round workgroup size (host side: selects the kernel instance)
 };
 
 // ------------------------------------------------------------ table setup
@@ -253,15 +254,16 @@ __device__ __forceinline__ void xcd_window(int nb, int* col, int* win) {
   *win = (int)(m - (long long)(*col) * nb);
 }
 
-constexpr int kRT = kRoundThreads;  // threads per round workgroup
 constexpr int kRun = 4;             // consecutive records / links per thread per step
 constexpr int kSuper = 1024;        // window nodes decided and expanded per pass
-constexpr int kNPT = kSuper / kRT;  // nodes per thread per pass
 
 // One round; mode 1 forces a fold-only launch (after an explicit single round).
-template <typename T, int SCHED>
-__global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_round(DiArgs<T> a, int r,
-                                                                                   int mode) {
+// NT threads per workgroup (512 or 1024: more loads in flight per window).
+template <typename T, int SCHED, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_round(DiArgs<T> a, int r,
+                                                                                  int mode) {
+  constexpr int kRT = NT;
+  constexpr int kNPT = kSuper / NT;  // nodes per thread per pass
   int ycol, b;  // vector column of the launch, window
   xcd_window(a.nb, &ycol, &b);
   const int vb = a.vmap ? a.vmap[ycol] : ycol;  // vector (0 for a single solve)
@@ -282,10 +284,12 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   int32_t* s_pre = reinterpret_cast<int32_t*>(s_base + nb);   // [nb+1] fold prefix, then ranks
   int32_t* s_soff = s_pre + (nb + 1);                         // [nb]
   int32_t* s_cap = s_soff + nb;                               // [nb]
+  // per node of the window: 0 not taken, 1 taken and not yet expanded, 2 expanded
+  uint8_t* s_state = reinterpret_cast<uint8_t*>(s_cap + nb);  // [W]
   __shared__ int32_t s_beo[kSuper + 1];
   __shared__ int64_t s_brow[kSuper];
   __shared__ double s_bsh[kSuper];
-  __shared__ double s_red[8 * (kRT / 64)];
+  __shared__ double s_red[block_reduce_k_scratch<NT, kSums>()];
   __shared__ long long s_scr[2 * (kRT / 64)];
 
   const int64_t j0 = (int64_t)b << a.wlog;
@@ -443,28 +447,38 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const uint32_t wmask = (uint32_t)W - 1u;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // nf, snd, sd, ssc, nnz, taken, edges
   mrem = 0.0;  // now: the largest untaken score of this window
+  // A. Decide for every node of the window (LDS only) before any push, so a
+  //    round takes one set S (reading 5) even though pushes that stay inside
+  //    the window are applied to its LDS copy at once.
+  for (int q = tid; q < W; q += kRT) {
+    const double f = q < wn ? win[q] : 0.0;
+    uint8_t st = 0;
+    if (f > 0.0) {
+      const int64_t j = j0 + q;
+      acc[0] += f;
+      acc[4] += 1.0;
+      int dg = -1;
+      if (SCHED != DI_SCHED_MEAN) dg = a.deg[j];
+      const double sc = node_score<SCHED>(f, dg, SCHED == DI_SCHED_OP ? a.indeg[j] : 0);
+      acc[3] += sc;
+      if (sc >= theta) st = 1;
+      else mrem = fmax(mrem, sc);
+    } else if (f != f) {
+      acc[0] = NAN;
+    }
+    s_state[q] = st;
+  }
+  __syncthreads();
+  int local_push = 0;  // some push stayed inside the window (its fluid is in LDS)
   for (int t0 = 0; t0 < wn; t0 += kSuper) {
-    // A. Decide for kNPT nodes per thread, then issue all their loads at once.
+    // B. Take the tile's nodes of S: load their link ranges and histories.
     double f[kNPT];
     bool tk[kNPT];
 #pragma unroll
     for (int u = 0; u < kNPT; ++u) {
       const int q = t0 + tid + u * kRT;
-      f[u] = q < wn ? win[q] : 0.0;
-      tk[u] = false;
-      if (f[u] > 0.0) {
-        const int64_t j = j0 + q;
-        acc[0] += f[u];
-        acc[4] += 1.0;
-        int dg = -1;
-        if (SCHED != DI_SCHED_MEAN) dg = a.deg[j];
-        const double sc = node_score<SCHED>(f[u], dg, SCHED == DI_SCHED_OP ? a.indeg[j] : 0);
-        acc[3] += sc;
-        if (sc >= theta) tk[u] = true;
-        else mrem = fmax(mrem, sc);
-      } else if (f[u] != f[u]) {
-        acc[0] = NAN;
-      }
+      tk[u] = q < wn && s_state[q] == 1;
+      f[u] = tk[u] ? win[q] : 0.0;
     }
     int64_t rs[kNPT];
     int dgs[kNPT];
@@ -484,6 +498,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       const int q = t0 + tid + u * kRT;
       Hv[j0 + q] = h[u] + f[u];
       win[q] = 0.0;
+      s_state[q] = 2;
       acc[5] += 1.0;
       if (dgs[u] > 0) {
         acc[1] += f[u];
@@ -493,7 +508,7 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         acc[2] += f[u];
       }
     }
-    // B. Stage the pushing nodes (thread-major order) with their link offsets.
+    // C. Stage the pushing nodes (thread-major order) with their link offsets.
     long long slot = 0, eoff = 0, ntile = 0, etile = 0;
     block_exscan2<kRT>(npush, nedge, s_scr, &slot, &eoff, &ntile, &etile);
     if (ntile == 0) continue;  // uniform
@@ -508,8 +523,11 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       eoff += dg;
     }
     __syncthreads();
-    // C. Push every staged link: each thread takes kRun consecutive links,
-    //    one search for the node of the first, then a forward walk.
+    // D. Push every staged link: each thread takes kRun consecutive links,
+    //    one search for the node of the first, then a forward walk.  A link
+    //    into this window whose target is not an S node still to be expanded
+    //    adds to the LDS copy directly (the fluid F holds for the next round,
+    //    rounded like a record); every other link writes a record.
     const int bcount = (int)ntile;
     for (long long t00 = (long long)tid * kRun; t00 < etile; t00 += (long long)kRT * kRun) {
       int k = upper_idx(s_beo, bcount, t00);
@@ -544,6 +562,11 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       for (int u = 0; u < kRun; ++u) {
         if (e[u] < 0) continue;
         const int w = (int)(dst[u] >> a.wlog);
+        if (w == b && s_state[dst[u] & wmask] != 1) {
+          atomicAdd(&win[dst[u] & wmask], (double)(T)v[u]);
+          local_push = 1;
+          continue;
+        }
         const int rank = atomicAdd(&s_pre[w], 1);
         if (rank < s_cap[w]) {
           PairT<T> pr;
@@ -564,13 +587,15 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   for (int q = tid; q < wn; q += kRT) Fv[j0 + q] = (T)win[q];
 
   // 4. This window's sums, added into its slot.
+  const int local_any = __syncthreads_or(local_push);
   const double edges = acc[6];
   acc[6] = 0.0;
   block_reduce_k<kRT, kSums>(acc, mrem, s_red);
   if (tid == 0) {
     acc[6] = edges;
-    // the window stays active while some node keeps untaken fluid
-    a.active[(int64_t)vb * nb + b] = acc[4] > acc[5] ? 1 : 0;
+    // the window stays active while some node keeps fluid: untaken, or
+    // pushed inside the window this round
+    a.active[(int64_t)vb * nb + b] = (acc[4] > acc[5] || local_any) ? 1 : 0;
     Slot* sl = slots + (r % 3) * kSlots + (b % kSlots);
 #pragma unroll
     for (int f = 0; f < kSums; ++f)
@@ -819,19 +844,19 @@ static int grid_for(int64_t n, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
 }
 
-template <typename T, int SCHED>
+template <typename T, int SCHED, int NT>
 static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, LaunchTimer* lt) {
   const size_t smem = round_lds_bytes(a.wlog, a.nb);
   // Dynamic LDS may use what the static part leaves of the workgroup limit
   // (set once per kernel instance; thread-safe initialisation).
   static const size_t dyn_limit = [] {
     hipFuncAttributes fa;
-    DI_HIP(hipFuncGetAttributes(&fa, (const void*)k_round<T, SCHED>));
+    DI_HIP(hipFuncGetAttributes(&fa, (const void*)k_round<T, SCHED, NT>));
     int dev = 0, lim = 0;
     DI_HIP(hipGetDevice(&dev));
     DI_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t dl = (size_t)lim - fa.sharedSizeBytes;
-    DI_HIP(hipFuncSetAttribute((const void*)k_round<T, SCHED>,
+    DI_HIP(hipFuncSetAttribute((const void*)k_round<T, SCHED, NT>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl));
     return dl;
   }();
@@ -841,9 +866,9 @@ static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, L
     // The runtime stamps the kernel's own begin/end into the event pair.
     hipEvent_t e0, e1;
     lt->next(&e0, &e1);
-    hipExtLaunchKernelGGL(k_round<T, SCHED>, grid, dim3(kRT), smem, s, e0, e1, 0, a, r, mode);
+    hipExtLaunchKernelGGL(k_round<T, SCHED, NT>, grid, dim3(NT), smem, s, e0, e1, 0, a, r, mode);
   } else {
-    k_round<T, SCHED><<<grid, kRT, smem, s>>>(a, r, mode);
+    k_round<T, SCHED, NT><<<grid, NT, smem, s>>>(a, r, mode);
   }
   DI_HIP(hipGetLastError());
 }
@@ -852,9 +877,18 @@ template <typename T>
 static void launch_round(const DiArgs<T>& a, int sched, int r, int mode, hipStream_t s,
                          LaunchTimer* lt = nullptr) {
   switch (sched) {
-    case DI_SCHED_OP2: launch_round_t<T, DI_SCHED_OP2>(a, r, mode, s, lt); break;
-    case DI_SCHED_OP: launch_round_t<T, DI_SCHED_OP>(a, r, mode, s, lt); break;
-    default: launch_round_t<T, DI_SCHED_MEAN>(a, r, mode, s, lt); break;
+    case DI_SCHED_OP2:
+      if (a.threads == 1024) launch_round_t<T, DI_SCHED_OP2, 1024>(a, r, mode, s, lt);
+      else launch_round_t<T, DI_SCHED_OP2, kRoundThreads>(a, r, mode, s, lt);
+      break;
+    case DI_SCHED_OP:
+      if (a.threads == 1024) launch_round_t<T, DI_SCHED_OP, 1024>(a, r, mode, s, lt);
+      else launch_round_t<T, DI_SCHED_OP, kRoundThreads>(a, r, mode, s, lt);
+      break;
+    default:
+      if (a.threads == 1024) launch_round_t<T, DI_SCHED_MEAN, 1024>(a, r, mode, s, lt);
+      else launch_round_t<T, DI_SCHED_MEAN, kRoundThreads>(a, r, mode, s, lt);
+      break;
   }
 }
 
@@ -956,7 +990,7 @@ static di_status status_of(const Ctl& h) {
 }
 
 struct TuneParams {
-  int sched, wlog, check_every;
+  int sched, wlog, check_every, threads;
   double c;
 };
 
@@ -979,6 +1013,8 @@ static TuneParams tune_params(Graph* g, const di_tune* tn, int mode, int precisi
   p.wlog = window_log2_for(g->n, tn ? tn->window_log2 : 0);
   DI_REQUIRE(p.wlog > 0, "graph has too many nodes for the window tables");
   p.check_every = tn ? std::max(0, tn->check_every) : 0;
+  p.threads = tn && tn->threads ? tn->threads : kRoundThreads;
+  DI_REQUIRE(p.threads == 512 || p.threads == 1024, "threads must be 0, 512 or 1024");
   return p;
 }
 
@@ -1005,6 +1041,7 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   T* F = resume ? static_cast<T*>(o->state_f) : ws->F.as<T>();
   double* H = resume ? o->state_h : ws->H.as<double>();
   DiArgs<T> a = make_args<T>(g, ws, o->d, o->tol, tp.c, max_rounds, F, H, 1);
+  a.threads = tp.threads;
   LaunchTimer lt(s, (o->flags & DI_TIMING) != 0);
   EventTimer timer(s);
   k_init<T><<<dim3(grid_for(g->n, 2048), 1), kBlock, 0, s>>>(a, vdev, resume ? 1 : 0, 0);
@@ -1084,6 +1121,7 @@ static di_status batch_impl(Graph* g, int32_t B, const int64_t* seed_ptr, const 
       DI_HIP(hipMemcpyAsync(d_w.p, seed_w + seed_ptr[b0], ptr[gb] * 8, hipMemcpyHostToDevice, s));
     DiArgs<T> a = make_args<T>(g, ws, o->d, o->tol, tp.c, max_rounds, ws->F.as<T>(),
                                ws->H.as<double>(), gb);
+    a.threads = tp.threads;
     EventTimer timer(s);
     k_init<T><<<dim3(grid_for(n, 256), gb), kBlock, 0, s>>>(a, nullptr, 0, 1);
     DI_HIP(hipGetLastError());
@@ -1414,6 +1452,7 @@ class SlotPoolT : public SlotPool {
   DiArgs<T> args(int k) {
     DiArgs<T> a = make_args<T>(g_, ws_, 0.85, 1e-6, tp_.c, 1000000, ws_->F.as<T>(),
                                ws_->H.as<double>(), k);
+    a.threads = tp_.threads;
     a.vmap = vmap_.as<int32_t>();
     a.vd = vd_.as<double>();
     a.vtol = vtol_.as<double>();

@@ -25,7 +25,7 @@ Graph::~Graph() {
 }
 
 size_t round_lds_bytes(int wlog, int nb) {
-  return ((size_t)8 << wlog) + (size_t)20 * nb + 16;
+  return ((size_t)9 << wlog) + (size_t)20 * nb + 16;
 }
 
 int window_log2_for(int64_t n, int requested) {

@@ -93,7 +93,16 @@ __device__ __forceinline__ double block_max(double v, double* scratch) {
 // Sums K values (and one max) across the block in one LDS round trip;
 // scratch holds (K+1) * NT/64 doubles.  Fixed order: deterministic.
 template <int NT, int K>
+constexpr int block_reduce_k_scratch() { return (K + 1) * (NT / 64 + 1); }
+
+// Block sums of K doubles and the block max of one more, returned to every
+// thread in a fixed order (deterministic).  Up to 512 threads every thread
+// adds the per-wave partials itself; larger blocks let wave 0 reduce them
+// (one partial per lane), so the registers used do not grow with the block.
+// scratch: block_reduce_k_scratch<NT, K>() doubles.
+template <int NT, int K>
 __device__ __forceinline__ void block_reduce_k(double (&v)[K], double& mx, double* scratch) {
+  constexpr int NW = NT / 64;
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
   mx = wave_max(mx);
@@ -101,21 +110,38 @@ __device__ __forceinline__ void block_reduce_k(double (&v)[K], double& mx, doubl
   __syncthreads();
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) scratch[k * (NT / 64) + wid] = v[k];
-    scratch[K * (NT / 64) + wid] = mx;
+    for (int k = 0; k < K; ++k) scratch[k * NW + wid] = v[k];
+    scratch[K * NW + wid] = mx;
   }
   __syncthreads();
+  if constexpr (NW <= 8) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double t = 0.0;
+    for (int k = 0; k < K; ++k) {
+      double t = 0.0;
 #pragma unroll
-    for (int i = 0; i < NT / 64; ++i) t += scratch[k * (NT / 64) + i];
-    v[k] = t;
+      for (int i = 0; i < NW; ++i) t += scratch[k * NW + i];
+      v[k] = t;
+    }
+    double m = scratch[K * NW];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) m = fmax(m, scratch[K * NW + i]);
+    mx = m;
+  } else {
+    double* out = scratch + (K + 1) * NW;
+    if (wid == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double t = wave_sum(lane < NW ? scratch[k * NW + lane] : 0.0);
+        if (lane == 0) out[k] = t;
+      }
+      const double m = wave_max(lane < NW ? scratch[K * NW + lane] : -INFINITY);
+      if (lane == 0) out[K] = m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = out[k];
+    mx = out[K];
   }
-  double m = scratch[K * (NT / 64)];
-#pragma unroll
-  for (int i = 1; i < NT / 64; ++i) m = fmax(m, scratch[K * (NT / 64) + i]);
-  mx = m;
   __syncthreads();
 }
 
