@@ -348,6 +348,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="library default knobs instead of di_autotune's choice")
+    ap.add_argument("--tune", metavar="SCHED:C:WLOG:THREADS",
+                    help="fixed knobs for the single solve instead of autotuning (profiling runs)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
@@ -386,7 +388,12 @@ def main():
 
     # ---- autotuner: the knobs every later solve on this graph uses
     tune_info = None
-    if not args.no_autotune:
+    fixed = None
+    if args.tune:
+        sc, c, wl_, th = args.tune.split(":")
+        fixed = di.make_tune(sc, float(c), int(wl_), threads=int(th))
+        tune_info = {"best": di.tune_dict(fixed), "fixed": True}
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         best, trials = di.autotune(G, "solve", d=args.d, tol=args.tol, precision=args.precision)
         ok = [t for t in trials if t["status"] == 0]
@@ -401,7 +408,7 @@ def main():
     # throughput; the same K solves again with per-launch HIP events (the
     # runtime stamps each round kernel's begin/end) give its launch durations.
     solve = lambda timing: di.solve(G, d=args.d, tol=args.tol, precision=args.precision,
-                                    timing=timing)
+                                    timing=timing, tune=fixed)
     sec, outs = time_steps(lambda: solve(False), args.steps, args.warmup)
     x_di = outs[-1][0]
     sec_timed, touts = time_steps(lambda: solve(True), args.steps, 0)
