@@ -17,6 +17,9 @@ Plain, slow, obviously-correct fp64 implementations written from the paper
   once (J_{i_n} replaced by the selector of a set), in C.
 * :func:`power` -- MAT-ITER X_{n+1} = dPX_n + (1-d)V from X_0 = 0 (Sections 2.1, 4),
   in C.
+* :func:`inject_update` -- the fluid a graph update injects, F' = F + d(P'-P)H
+  (updating equation, Section 3.3); :func:`set_step_signed` -- a set step on
+  fluid of either sign (|F_i| against the threshold), in numpy.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library
@@ -221,3 +224,38 @@ def limit(g, d: float, v=None, tol: float = 1e-14):
     if g.n <= 2000:
         return dense_exact(g, d, v)[1]
     return power(g, d, tol, v)["x"]
+
+
+# ------------------------------------------------------------ graph updates
+
+def transition_sparse(g):
+    """Sparse P (CSC) with P[j, i] = (#links i->j) / outdeg(i); dangling columns
+    are zero (Section 2.1)."""
+    import scipy.sparse as sp
+    n, rp, ci = _csr(g)
+    deg = np.diff(rp)
+    src = np.repeat(np.arange(n), deg)
+    return sp.csc_matrix((1.0 / deg[src], (ci.astype(np.int64), src)), shape=(n, n))
+
+
+def inject_update(g_old, g_new, d: float, F, H):
+    """Updating equation (Section 3.3): when P becomes P' with the state (F, H)
+    of a D-iteration on P, the D-iteration continues on P' from
+    F' = F + d (P' - P) H (Theorem 4: H + F' = F_0 + d P' H).  fp64."""
+    H = np.asarray(H, dtype=np.float64)
+    return (np.asarray(F, dtype=np.float64) + d * (transition_sparse(g_new) @ H)
+            - d * (transition_sparse(g_old) @ H))
+
+
+def set_step_signed(g, d: float, theta: float, F, H):
+    """One set step on fluid of either sign: S = {i : F_i != 0, |F_i| >= theta};
+    H += F on S, F = 0 on S, then F += d P (the fluid sent).  Returns
+    (F', H', taken mask)."""
+    F = np.array(F, dtype=np.float64)
+    H = np.array(H, dtype=np.float64)
+    S = (F != 0.0) & (np.abs(F) >= theta)
+    sent = np.where(S, F, 0.0)
+    H += sent
+    F -= sent
+    F += d * (transition_sparse(g) @ sent)
+    return F, H, S

@@ -298,3 +298,70 @@ def test_threshold_variant_uses_fewer_elementary_steps():
     p = oracle.power(g, D, 1e-8)
     s = oracle.diter_sets(g, D, 1e-8, c=1.0)
     assert s["stats"]["edges"] < p["stats"]["edges"]
+
+
+# ------------------------------------------------- graph updates (Section 3.3)
+
+def _update_pair(seed):
+    g0 = wl.random_small(40, 160, seed=seed, p_dangling=0.15)
+    return g0, wl.modify_graph(g0, 0.25, seed=seed + 100)
+
+
+def test_update_injection_gives_theorem1_for_the_new_graph():
+    """After F' = F + d(P'-P)H, H + F' = F_0 + dP'H componentwise (the
+    restart condition of the updating equation)."""
+    g0, g1 = _update_pair(1)
+    r = oracle.diter(g0, D, 1e-3, order="per")
+    F1 = oracle.inject_update(g0, g1, D, r["F"], r["H"])
+    P1 = oracle.transition_dense(g1)
+    assert np.abs(r["H"] + F1 - ((1 - D) / g1.n + D * P1 @ r["H"])).max() < 1e-14
+
+
+def test_update_equation_theorem3():
+    """H'_inf - H_inf = (I - dP')^{-1} d (P' - P) H_inf, with both limits from
+    dense solves of their definitions."""
+    g0, g1 = _update_pair(3)
+    Y0, Y1 = oracle.dense_exact(g0, D)[0], oracle.dense_exact(g1, D)[0]
+    inj = oracle.inject_update(g0, g1, D, np.zeros(g0.n), Y0)
+    Z = np.linalg.solve(np.eye(g1.n) - D * oracle.transition_dense(g1), inj)
+    np.testing.assert_allclose(Z, Y1 - Y0, atol=1e-13)
+
+
+def test_restart_after_update_reaches_the_new_limit_theorem4():
+    """Continuing the D-iteration on P' from the injected state converges to
+    the solution for P' (Theorem 4), although the injected fluid has both signs."""
+    g0, g1 = _update_pair(2)
+    r = oracle.diter(g0, D, 1e-4, order="per")
+    F1 = oracle.inject_update(g0, g1, D, r["F"], r["H"])
+    assert (F1 < 0).any() and (F1 > 0).any()
+    r1 = oracle.diter(g1, D, 1e-14, order="per", state=(F1, r["H"]))
+    assert r1["converged"]
+    np.testing.assert_allclose(r1["x"], oracle.dense_exact(g1, D)[1], atol=1e-12)
+
+
+def test_signed_set_steps_keep_theorem1_and_converge():
+    g0, g1 = _update_pair(4)
+    r = oracle.diter(g0, D, 1e-3, order="per")
+    F, H = oracle.inject_update(g0, g1, D, r["F"], r["H"]), r["H"].copy()
+    P1 = oracle.transition_dense(g1)
+    for _ in range(400):
+        nf = np.abs(F).sum()
+        if nf < 1e-13:
+            break
+        F, H, S = oracle.set_step_signed(g1, D, nf / g1.n, F, H)
+        assert S.any()
+        assert np.abs(H + F - ((1 - D) / g1.n + D * P1 @ H)).max() < 1e-14
+    assert np.abs(F).sum() < 1e-13
+    np.testing.assert_allclose((H + F) / (H + F).sum(), oracle.dense_exact(g1, D)[1], atol=1e-12)
+
+
+def test_modify_graph_changes_only_the_chosen_rows():
+    g0 = wl.random_small(200, 1000, seed=9, p_dangling=0.1)
+    g1 = wl.modify_graph(g0, 0.1, seed=10)
+    d0, d1 = np.diff(g0.row_ptr), np.diff(g1.row_ptr)
+    same = [i for i in range(g0.n) if d0[i] == d1[i] and np.array_equal(
+        g0.col_idx[g0.row_ptr[i]:g0.row_ptr[i + 1]], g1.col_idx[g1.row_ptr[i]:g1.row_ptr[i + 1]])]
+    assert 170 <= len(same) < 200
+    for i in sorted(set(range(g1.n)) - set(same)):  # new rows: no self-links, no repeats
+        row = g1.col_idx[g1.row_ptr[i]:g1.row_ptr[i + 1]]
+        assert len(set(row.tolist())) == len(row) and i not in row

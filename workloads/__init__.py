@@ -192,6 +192,30 @@ def random_small(n: int, m: int, seed: int, p_dangling: float = 0.2,
 
 # ------------------------------------------------------------ other inputs
 
+def modify_graph(g: Graph, frac: float, seed: int) -> Graph:
+    """A changed copy of g (a graph update): a fraction `frac` of the nodes,
+    chosen uniformly, get a new out-link list -- degree changed by -2..+2
+    (10% of them become dangling), targets uniform over the other nodes,
+    without repeats.  The other rows are kept as they are."""
+    rng = np.random.default_rng(seed)
+    n = g.n
+    deg = np.diff(g.row_ptr)
+    chosen = np.zeros(n, dtype=bool)
+    chosen[rng.choice(n, size=max(1, int(frac * n)), replace=False)] = True
+    src_old = np.repeat(np.arange(n, dtype=np.int64), deg)
+    keep = ~chosen[src_old]
+    srcs, dsts = [src_old[keep]], [g.col_idx[keep].astype(np.int64)]
+    for i in np.nonzero(chosen)[0]:
+        k = 0 if rng.random() < 0.1 else int(np.clip(deg[i] + rng.integers(-2, 3), 1, n - 1))
+        if k == 0:
+            continue
+        t = rng.choice(n - 1, size=k, replace=False)
+        t = t + (t >= i)  # no self-link
+        srcs.append(np.full(k, i, dtype=np.int64))
+        dsts.append(t.astype(np.int64))
+    return from_edges(n, np.concatenate(srcs), np.concatenate(dsts), g.name + "-mod")
+
+
 def uniform_v(n: int) -> np.ndarray:
     return np.full(n, 1.0 / n)
 
