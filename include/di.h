@@ -159,7 +159,7 @@ di_status di_power_solve(const di_graph* g, const double* v, const di_opts* opts
 
 /*
  * One threshold round on caller-provided device state (the kernel step of a
- * di_solve round): every node with F_i > 0 and F_i >= theta (compared in
+ * di_solve round): every node with F_i != 0 and |F_i| >= theta (compared in
  * fp64) is taken -- H_i += F_i, F_i = 0 -- and its fluid is pushed,
  * d F_i p(j,i) to each child j (the set form of the Section 2.2 recurrences).
  * F: device float[n] (DI_FP32_FLUID) or double[n] (DI_FP64); H: device
@@ -169,6 +169,20 @@ di_status di_power_solve(const di_graph* g, const double* v, const di_opts* opts
 di_status di_diffuse_round(const di_graph* g, int32_t precision, double d, double theta,
                            void* F, double* H, int64_t* taken_nodes, int64_t* taken_edges,
                            void* stream);
+
+/*
+ * Graph update (the updating equation of Section 3.3).  The graph changes
+ * from P (g_old) to P' (g_new), both with the same n, while a solve on P is
+ * under way (or done) with device state F (float[n] for DI_FP32_FLUID,
+ * double[n] for DI_FP64) and H (double[n]).  Adds d (P' - P) H to F (each
+ * node's two in-link sums in fp64, one rounding into F); afterwards
+ * H + F = F_0 + d P' H holds (Theorem 1 for P'), and di_solve on g_new with
+ * DI_RESUME and this state continues to the solution of X = d P' X + F_0
+ * (Theorem 4).  The injected fluid may be negative: rounds take nodes on
+ * |F_i|, the residual is ||F||_1.  DI_EINVAL if n differs.
+ */
+di_status di_inject_update(const di_graph* g_old, const di_graph* g_new, int32_t precision,
+                           double d, void* F, const double* H, void* stream);
 
 /* ---------------------------------------------------------------- batches */
 

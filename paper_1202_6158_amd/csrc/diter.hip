@@ -65,7 +65,7 @@ struct DiArgs {
   Slot* slots;            // [nvec][3][kSlots] round sums, round r uses set r % 3
   uint8_t* active;        // [nvec][nb] window held fluid after its last round
   Ctl* ctl;               // [nvec]
-  double* flacc;          // [nvec][1024] flush partial sums
+  double* flacc;          // [nvec][kFlushAcc] flush partial sums
   int64_t mrec;           // records per vector buffer
   int nvec;
   // Serving: blockIdx.y -> vector slot, and per-slot round index, d and tol
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DiArgs<T> a, const double* __re
     c->theta = a.theta0;
     c->nodes_total = c->edges_total = 0;
     c->last_taken = c->last_edges = 0;
-    for (int k = 0; k < 4; ++k) c->fl[k] = 0.0;
+    for (int k = 0; k < kFlushSums; ++k) c->fl[k] = 0.0;
   }
 }
 
@@ -451,15 +451,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   //    round takes one set S (reading 5) even though pushes that stay inside
   //    the window are applied to its LDS copy at once.
   for (int q = tid; q < W; q += kRT) {
-    const double f = q < wn ? win[q] : 0.0;
+    // Fluid may be signed after an update of the graph (Section 3.3): the
+    // threshold and the residual use |F_i|.
+    const double f = q < wn ? win[q] : 0.0, af = fabs(f);
     uint8_t st = 0;
-    if (f > 0.0) {
+    if (af > 0.0) {
       const int64_t j = j0 + q;
-      acc[0] += f;
+      acc[0] += af;
       acc[4] += 1.0;
       int dg = -1;
       if (SCHED != DI_SCHED_MEAN) dg = a.deg[j];
-      const double sc = node_score<SCHED>(f, dg, SCHED == DI_SCHED_OP ? a.indeg[j] : 0);
+      const double sc = node_score<SCHED>(af, dg, SCHED == DI_SCHED_OP ? a.indeg[j] : 0);
       acc[3] += sc;
       if (sc >= theta) st = 1;
       else mrem = fmax(mrem, sc);
@@ -501,11 +503,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       s_state[q] = 2;
       acc[5] += 1.0;
       if (dgs[u] > 0) {
-        acc[1] += f[u];
+        acc[1] += fabs(f[u]);
         ++npush;
         nedge += dgs[u];
       } else {
-        acc[2] += f[u];
+        acc[2] += fabs(f[u]);
       }
     }
     // C. Stage the pushing nodes (thread-major order) with their link offsets.
@@ -604,33 +606,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   }
 }
 
-// Flush sums of vector blockIdx.y: sum(H+F), sum(H), sum(F), sum over
-// dangling nodes of H, as per-block partials spread over 256 slots.
+// Flush sums of vector blockIdx.y: sum(H+F), sum(H), sum|F|, sum over
+// dangling nodes of H, sum(F), as per-block partials spread over 256 slots.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_flush_sum(DiArgs<T> a) {
   __shared__ double s_red[kBlock / 64];
   const int vb = a.vmap ? a.vmap[blockIdx.y] : blockIdx.y;
   const T* F = a.F + (int64_t)vb * a.n;
   const double* H = a.H + (int64_t)vb * a.n;
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
        i += (int64_t)gridDim.x * kBlock) {
     const double h = H[i], f = (double)F[i];
     s0 += h + f;
     s1 += h;
-    s2 += f;
+    s2 += fabs(f);
     if (a.deg[i] == 0) s3 += h;
+    s4 += f;
   }
   s0 = block_sum(s0, s_red);
   s1 = block_sum(s1, s_red);
   s2 = block_sum(s2, s_red);
   s3 = block_sum(s3, s_red);
+  s4 = block_sum(s4, s_red);
   if (threadIdx.x == 0) {
-    double* slot = a.flacc + (int64_t)vb * 1024 + 4 * (blockIdx.x & 255);
+    double* slot = a.flacc + (int64_t)vb * kFlushAcc + kFlushSums * (blockIdx.x % kFlushSlots);
     unsafeAtomicAdd(slot + 0, s0);
     unsafeAtomicAdd(slot + 1, s1);
     unsafeAtomicAdd(slot + 2, s2);
     unsafeAtomicAdd(slot + 3, s3);
+    unsafeAtomicAdd(slot + 4, s4);
   }
 }
 
@@ -639,9 +644,9 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_flush_reduce(DiArgs<T> a) {
   __shared__ double s_red[kBlock / 64];
   const int vb = a.vmap ? a.vmap[blockIdx.x] : blockIdx.x;
-  const double* acc = a.flacc + (int64_t)vb * 1024;
-  for (int k = 0; k < 4; ++k) {
-    const double v = block_sum(acc[4 * threadIdx.x + k], s_red);
+  const double* acc = a.flacc + (int64_t)vb * kFlushAcc;
+  for (int k = 0; k < kFlushSums; ++k) {
+    const double v = block_sum(acc[kFlushSums * threadIdx.x + k], s_red);
     if (threadIdx.x == 0) a.ctl[vb].fl[k] = v;
   }
 }
@@ -671,7 +676,7 @@ __global__ void k_zero(double* p, int64_t n) {
 static int64_t bytes_per_vector(int64_t n, int64_t m, int nb, int precision) {
   const int64_t fs = precision == DI_FP64 ? 8 : 4, ps = precision == DI_FP64 ? 16 : 8;
   return n * (fs + 8) + 2 * std::max<int64_t>(m, 1) * ps + 2 * (int64_t)nb * nb * 4 +
-         3 * kSlots * (int64_t)sizeof(Slot) + nb + (int64_t)sizeof(Ctl) + 1024 * 8;
+         3 * kSlots * (int64_t)sizeof(Slot) + nb + (int64_t)sizeof(Ctl) + kFlushAcc * 8;
 }
 
 // Workspace for nvec vectors of window 2^wlog (single solves use nvec = 1).
@@ -696,7 +701,7 @@ static Workspace* make_workspace(Graph* g, int precision, int wlog, int nvec) {
     }
     ws->bstart.alloc((nb + 1) * 8);
     ws->ctl.alloc(nvec * sizeof(Ctl));
-    ws->flacc.alloc(nvec * 1024 * 8);
+    ws->flacc.alloc(nvec * kFlushAcc * 8);
     ws->active.alloc(nvec * (int64_t)nb);
     for (int k = 0; k < 2; ++k) {
       ws->pairs[k].alloc(nvec * mrec * (precision == DI_FP64 ? 16 : 8));
@@ -940,7 +945,7 @@ static void run_rounds(const DiArgs<T>& a, Workspace* ws, int sched, int check_e
 template <typename T>
 __global__ void k_zero_flush(DiArgs<T> a) {
   const int vb = a.vmap ? a.vmap[blockIdx.x] : blockIdx.x;
-  for (int k = threadIdx.x; k < 1024; k += blockDim.x) a.flacc[(int64_t)vb * 1024 + k] = 0.0;
+  for (int k = threadIdx.x; k < kFlushAcc; k += blockDim.x) a.flacc[(int64_t)vb * kFlushAcc + k] = 0.0;
 }
 
 template <typename T>
@@ -964,7 +969,7 @@ static void fill_stats(const Ctl& h, const di_opts* o, double secs, di_stats* st
   st->residual_l1 = nf;
   st->err_bound_l1 = o->normalize ? (S > 0 ? 2.0 * d * nf / ((1.0 - d) * S) : 0.0)
                                   : d * nf / (1.0 - d);
-  st->mass_drift = h.fl[1] + (h.fl[2] + d * h.fl[3]) / (1.0 - d) - 1.0;
+  st->mass_drift = h.fl[1] + (h.fl[4] + d * h.fl[3]) / (1.0 - d) - 1.0;
   st->seconds = secs;
   st->rounds = h.stop_round + 1;
   st->nodes_diffused = h.nodes_total;

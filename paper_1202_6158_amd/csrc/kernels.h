@@ -38,6 +38,10 @@ struct alignas(64) Slot {
   unsigned long long mrem;
 };
 
+constexpr int kFlushSums = 5;       // sums the flush takes per vector
+constexpr int kFlushSlots = 256;    // partial-sum slots per flush sum
+constexpr int kFlushAcc = kFlushSums * kFlushSlots;
+
 // Control block in device memory.  Each field is written by workgroup 0 of
 // one launch and read only by later launches.
 struct Ctl {
@@ -49,7 +53,8 @@ struct Ctl {
   double theta;    // threshold of the latest round
   long long nodes_total, edges_total;  // diffusions and out-links used
   long long last_taken, last_edges;    // of the latest round
-  double fl[4];    // flush sums: sum(H+F), sum(H), sum(F), sum over dangling of H
+  // flush sums: sum(H+F), sum(H), sum|F|, sum over dangling of H, sum(F)
+  double fl[kFlushSums];
 };
 
 __device__ __forceinline__ double wave_sum(double v) {

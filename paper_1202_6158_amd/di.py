@@ -115,6 +115,7 @@ _SIGS = {
     "di_power_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_diffuse_round": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P],
     "di_solve_batch": [_P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _P],
+    "di_inject_update": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P, _P],
     "di_autotune": [_P, ctypes.c_int32, ctypes.POINTER(Opts), ctypes.c_int32, _P, _P,
                     ctypes.POINTER(Tune), _P, ctypes.c_int32, _P, _P],
     "di_server_create": [ctypes.POINTER(ServerOpts), _P],
@@ -316,6 +317,15 @@ def solve_batch(graph: Graph, seed_ptr, seeds, seed_w=None, d=0.85, tol=1e-6, pr
                              ctypes.byref(o), _ptr(x), st, _stream(stream))
     _check(rc, allow=(ENOTCONV,) if allow_notconv else ())
     return x, [st[b].as_dict() for b in range(B)]
+
+
+def inject_update(old: Graph, new: Graph, F, H, d=0.85, stream=None):
+    """di_inject_update: F += d (P_new - P_old) H on torch cuda tensors (F
+    float32 or float64, H float64), in place."""
+    torch = _torch()
+    prec = "fp64" if F.dtype == torch.float64 else "fp32"
+    _check(_lib.di_inject_update(old.handle, new.handle, PRECISION[prec], float(d), _ptr(F),
+                                 _ptr(H), _stream(stream)))
 
 
 TUNE_SOLVE = 0

@@ -1,0 +1,103 @@
+"""GPU tests of the graph update (updating equation, Section 3.3): the fluid
+injection F += d(P'-P)H against the oracle's, one round on signed fluid
+against the oracle's signed set step, and the full flow -- solve on P, change
+the graph, inject, resume on P' -- against the exact limit of P' (Theorem 4),
+with less work than a fresh solve."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+D = 0.85
+
+
+@pytest.fixture(scope="module")
+def di():
+    import torch
+    from paper_1202_6158_amd import di as _di
+    torch.cuda.set_device(0)
+    return _di
+
+
+@pytest.fixture(scope="module")
+def pair():
+    g0 = wl.recipe("pagerank-10k")
+    return g0, wl.modify_graph(g0, 0.01, seed=77)
+
+
+def _state(di, G, g, prec, tol):
+    import torch
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    F = torch.full((g.n,), (1 - D) / g.n, dtype=dt, device="cuda")
+    H = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    di.solve(G, d=D, tol=tol, precision=prec, state=(F, H))
+    return F, H
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_inject_matches_oracle(di, pair, prec):
+    g0, g1 = pair
+    G0, G1 = di.Graph(g0), di.Graph(g1)
+    F, H = _state(di, G0, g0, prec, 1e-5)
+    F0, H0 = F.cpu().numpy().astype(np.float64), H.cpu().numpy()
+    di.inject_update(G0, G1, F, H, d=D)
+    ref = oracle.inject_update(g0, g1, D, F0, H0)
+    got = F.cpu().numpy().astype(np.float64)
+    if prec == "fp64":
+        assert np.abs(got - ref).max() <= 1e-15 * max(1.0, np.abs(ref).max())
+    else:  # one rounding of the fp64 sum into fp32
+        assert np.all(np.abs(got - ref) <= np.spacing(np.abs(ref).astype(np.float32)) + 1e-30)
+    assert (ref < 0).any()  # the injection mixes signs
+    assert np.array_equal(H.cpu().numpy(), H0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_round_on_signed_fluid_matches_oracle(di, pair, prec):
+    import torch
+    g0, g1 = pair
+    G0, G1 = di.Graph(g0), di.Graph(g1)
+    F, H = _state(di, G0, g0, prec, 1e-5)
+    di.inject_update(G0, G1, F, H, d=D)
+    Fs, Hs = F.cpu().numpy().astype(np.float64), H.cpu().numpy()
+    theta = float(np.abs(Fs).sum() / g1.n)
+    di.diffuse_round(G1, F, H, theta, d=D)
+    Fr, Hr, S = oracle.set_step_signed(g1, D, theta, Fs, Hs)
+    Hg, Fg = H.cpu().numpy(), F.cpu().numpy().astype(np.float64)
+    assert np.array_equal(Hg, Hr)  # same set taken, F_i added to H_i once in fp64
+    # fluid: k pushes into a node, each rounded once, summed in any order
+    src, dst = g1.edges()
+    share = np.zeros(g1.n)
+    share[S] = D * Fs[S] / np.maximum(g1.outdeg[S], 1)
+    push = np.abs(share[src])
+    k = np.bincount(dst, weights=(push > 0).astype(float), minlength=g1.n)
+    mag = np.abs(np.where(S, 0.0, Fs)) + np.bincount(dst, weights=push, minlength=g1.n)
+    eps = 2.0 ** -24 if prec == "fp32" else 2.0 ** -53
+    assert np.all(np.abs(Fg - Fr) <= (k + 2) * 2 * eps * mag + 1e-300)
+
+
+@pytest.mark.parametrize("prec,tol,eps", [("fp64", 1e-11, 1e-12), ("fp32", 1e-8, 1e-6)])
+def test_update_then_resume_reaches_new_limit(di, pair, prec, tol, eps):
+    g0, g1 = pair
+    G0, G1 = di.Graph(g0), di.Graph(g1)
+    F, H = _state(di, G0, g0, prec, tol)
+    di.inject_update(G0, G1, F, H, d=D)
+    x, st = di.solve(G1, d=D, tol=tol, precision=prec, state=(F, H))
+    xs = oracle.limit(g1, D, tol=1e-14)
+    assert st["residual_l1"] < tol
+    assert float(np.abs(x.cpu().numpy() - xs).sum()) <= st["err_bound_l1"] + eps
+    assert abs(st["mass_drift"]) < (1e-12 if prec == "fp64" else 1e-5)
+    # a 1% change costs far less than solving P' from scratch
+    _, fresh = di.solve(G1, d=D, tol=tol, precision=prec)
+    assert st["edges_diffused"] < 0.6 * fresh["edges_diffused"]
+
+
+def test_inject_rejects_mismatched_graphs(di):
+    import torch
+    a, b = di.Graph(wl.cycle(10)), di.Graph(wl.cycle(11))
+    F = torch.zeros(11, dtype=torch.float64, device="cuda")
+    H = torch.zeros(11, dtype=torch.float64, device="cuda")
+    with pytest.raises(di.DiError) as e:
+        di.inject_update(a, b, F, H)
+    assert e.value.status == di.EINVAL
