@@ -13,6 +13,8 @@ resident in HBM.  Prints ONE JSON line with:
   comparator      the GPU power iteration (pull) on the same graph and stop rule
   cpu_baseline    the CPU oracle's sequential D-iteration on the host
   ppr_batch       batched personalised PageRank (256 seed sets, 1e-6)
+  update          a 1% graph change: injected fluid + resume vs a fresh solve
+  paper_replay    the paper's six simulation scenarios: links diffused vs power iteration
   serve           the continuous-batching server on a short Poisson stream
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
@@ -201,6 +203,60 @@ def bench_ppr_batch(di, G, g, args):
             "edges_diffused": int(sum(s["edges_diffused"] for s in stats))}
 
 
+def bench_update(di, G, g, args):
+    """Graph update (Section 3.3): 1% of the nodes get new out-link lists;
+    the converged state of the old graph plus the injected fluid d(P'-P)H is
+    resumed on the new graph, against a fresh solve of the new graph."""
+    import torch
+    import workloads as wl
+    g1 = wl.modify_graph(g, 0.01, seed=77)
+    G1 = di.Graph(g1)
+    dt = torch.float32 if args.precision == "fp32" else torch.float64
+    reps, t_upd, t_fresh, st_u, st_f = 3, [], [], None, None
+    for _ in range(reps):
+        F = torch.full((g.n,), (1 - args.d) / g.n, dtype=dt, device="cuda")
+        H = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        di.solve(G, d=args.d, tol=args.tol, precision=args.precision, state=(F, H))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        di.inject_update(G, G1, F, H, d=args.d)
+        _, st_u = di.solve(G1, d=args.d, tol=args.tol, precision=args.precision, state=(F, H))
+        torch.cuda.synchronize()
+        t_upd.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        _, st_f = di.solve(G1, d=args.d, tol=args.tol, precision=args.precision)
+        torch.cuda.synchronize()
+        t_fresh.append(time.perf_counter() - t0)
+    return {"changed_nodes": int(0.01 * g.n), "links_new_graph": g1.m,
+            "update_ms": 1e3 * min(t_upd), "fresh_ms": 1e3 * min(t_fresh),
+            "speedup": min(t_fresh) / min(t_upd),
+            "update_rounds": st_u["rounds"], "update_links": st_u["edges_diffused"],
+            "fresh_rounds": st_f["rounds"], "fresh_links": st_f["edges_diffused"],
+            "update_residual_l1": st_u["residual_l1"]}
+
+
+def bench_paper_replay(di, args):
+    """The paper's six simulation scenarios (Section 5): links diffused by the
+    D-iteration (its elementary steps) and by the power iteration (L per
+    product), device times, fp64, same stop rule."""
+    import workloads as wl
+    rows = {}
+    for name in wl.PAPER_SCENARIOS:
+        g = wl.paper_scenario(name)
+        G = di.Graph(g)
+        di.solve(G, d=args.d, tol=args.tol, precision="fp64")
+        _, st = di.solve(G, d=args.d, tol=args.tol, precision="fp64")
+        di.power_solve(G, d=args.d, tol=args.tol, precision="fp64")
+        _, sp = di.power_solve(G, d=args.d, tol=args.tol, precision="fp64")
+        rows[name] = {"n": g.n, "links": g.m, "dangling": g.n_dangling,
+                      "diter_links": st["edges_diffused"], "diter_rounds": st["rounds"],
+                      "diter_ms": 1e3 * st["seconds"],
+                      "power_links": sp["rounds"] * g.m, "power_products": sp["rounds"],
+                      "power_ms": 1e3 * sp["seconds"],
+                      "link_ratio": sp["rounds"] * g.m / max(1, st["edges_diffused"])}
+    return rows
+
+
 SERVE_GRAPHS = ("serve-100k", "serve-500k", "serve-1m", "serve-5m")
 SERVE_TOLS = (1e-4, 1e-6, 1e-8)
 
@@ -346,6 +402,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ppr", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-update", action="store_true")
+    ap.add_argument("--no-replay", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="library default knobs instead of di_autotune's choice")
     ap.add_argument("--tune", metavar="SCHED:C:WLOG:THREADS",
@@ -479,6 +537,10 @@ def main():
     }
     if not args.no_ppr:
         out["ppr_batch"] = bench_ppr_batch(di, G, g, args)
+    if not args.no_update:
+        out["update"] = bench_update(di, G, g, args)
+    if not args.no_replay:
+        out["paper_replay"] = bench_paper_replay(di, args)
     if not args.no_serve:
         out["serve"] = bench_serve(di, args)
     if args.copy_calibration:
