@@ -174,8 +174,9 @@ di_status di_diffuse_round(const di_graph* g, int32_t precision, double d, doubl
  * Graph update (the updating equation of Section 3.3).  The graph changes
  * from P (g_old) to P' (g_new), both with the same n, while a solve on P is
  * under way (or done) with device state F (float[n] for DI_FP32_FLUID,
- * double[n] for DI_FP64) and H (double[n]).  Adds d (P' - P) H to F (each
- * node's two in-link sums in fp64, one rounding into F); afterwards
+ * double[n] for DI_FP64) and H (double[n]).  Adds d (P' - P) H to F (only
+ * the out-link rows that differ between the graphs push, +H_i p'(j,i) and
+ * -H_i p(j,i), summed in fp64; one rounding into F); afterwards
  * H + F = F_0 + d P' H holds (Theorem 1 for P'), and di_solve on g_new with
  * DI_RESUME and this state continues to the solution of X = d P' X + F_0
  * (Theorem 4).  The injected fluid may be negative: rounds take nodes on

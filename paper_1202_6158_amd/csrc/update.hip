@@ -10,46 +10,62 @@
 #include <algorithm>
 #include <cmath>
 
+#include "internal.h"
 #include "kernels.h"
 
 namespace di {
 
 namespace {
 
-// F_j += d (sum over in-links i of j in P' of H_i p'(j,i) - the same in P),
-// one thread per node, both sums in fp64 over the in-link lists (sorted by
-// source, so an unchanged row cancels exactly), one rounding into F.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_inject(
-    int64_t n, double d, const int64_t* __restrict__ ip1, const int32_t* __restrict__ is1,
-    const double* __restrict__ iw1, const int32_t* __restrict__ deg1,
-    const int64_t* __restrict__ ip0, const int32_t* __restrict__ is0,
-    const double* __restrict__ iw0, const int32_t* __restrict__ deg0,
-    const double* __restrict__ H, T* __restrict__ F) {
+// delta += (P' - P) H restricted to the rows that differ: a node whose
+// out-links (and weights) are the same in both graphs contributes nothing, so
+// only the changed rows push, +H_i p'(j,i) to the new children and
+// -H_i p(j,i) to the old ones (fp64 atomics; a change touches few rows).
+__global__ __launch_bounds__(kBlock) void k_inject_rows(
+    int64_t n, const int64_t* __restrict__ rp0, const int32_t* __restrict__ c0,
+    const double* __restrict__ w0, const int64_t* __restrict__ rp1,
+    const int32_t* __restrict__ c1, const double* __restrict__ w1,
+    const double* __restrict__ H, double* __restrict__ delta) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
-    double s1 = 0.0, s0 = 0.0;
-    for (int64_t e = ip1[j]; e < ip1[j + 1]; ++e) {
-      const int32_t i = is1[e];
-      s1 += H[i] * (iw1 ? iw1[e] : 1.0 / (double)deg1[i]);
-    }
-    for (int64_t e = ip0[j]; e < ip0[j + 1]; ++e) {
-      const int32_t i = is0[e];
-      s0 += H[i] * (iw0 ? iw0[e] : 1.0 / (double)deg0[i]);
-    }
-    if (s1 != s0) F[j] = (T)((double)F[j] + d * (s1 - s0));
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double h = H[i];
+    if (h == 0.0) continue;
+    const int64_t a0 = rp0[i], b0 = rp0[i + 1], a1 = rp1[i], b1 = rp1[i + 1];
+    bool same = b0 - a0 == b1 - a1 && (w0 == nullptr) == (w1 == nullptr);
+    for (int64_t k = 0; same && k < b0 - a0; ++k)
+      same = c0[a0 + k] == c1[a1 + k] && (!w0 || w0[a0 + k] == w1[a1 + k]);
+    if (same) continue;
+    for (int64_t e = a1; e < b1; ++e)
+      atomicAdd(&delta[c1[e]], h * (w1 ? w1[e] : 1.0 / (double)(b1 - a1)));
+    for (int64_t e = a0; e < b0; ++e)
+      atomicAdd(&delta[c0[e]], -h * (w0 ? w0[e] : 1.0 / (double)(b0 - a0)));
   }
+}
+
+// F_j += d delta_j, one rounding into the fluid type.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_inject_apply(int64_t n, double d,
+                                                         const double* __restrict__ delta,
+                                                         T* __restrict__ F) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride)
+    if (delta[j] != 0.0) F[j] = (T)((double)F[j] + d * delta[j]);
 }
 
 template <typename T>
 void inject(const Graph* g0, const Graph* g1, double d, T* F, const double* H, hipStream_t s) {
   const int64_t n = g1->n;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 8192));
-  k_inject<T><<<grid, kBlock, 0, s>>>(
-      n, d, g1->in_ptr.as<int64_t>(), g1->in_src.as<int32_t>(),
-      g1->weighted ? g1->in_w.as<double>() : nullptr, g1->deg.as<int32_t>(),
-      g0->in_ptr.as<int64_t>(), g0->in_src.as<int32_t>(),
-      g0->weighted ? g0->in_w.as<double>() : nullptr, g0->deg.as<int32_t>(), H, F);
+  DevBuf delta;
+  delta.alloc(n * 8);
+  DI_HIP(hipMemsetAsync(delta.p, 0, n * 8, s));
+  k_inject_rows<<<grid, kBlock, 0, s>>>(
+      n, g0->row_ptr.as<int64_t>(), g0->col.as<int32_t>(),
+      g0->weighted ? g0->w.as<double>() : nullptr, g1->row_ptr.as<int64_t>(),
+      g1->col.as<int32_t>(), g1->weighted ? g1->w.as<double>() : nullptr, H,
+      delta.as<double>());
+  DI_HIP(hipGetLastError());
+  k_inject_apply<T><<<grid, kBlock, 0, s>>>(n, d, delta.as<double>(), F);
   DI_HIP(hipGetLastError());
   DI_HIP(hipStreamSynchronize(s));
 }
