@@ -259,3 +259,43 @@ def set_step_signed(g, d: float, theta: float, F, H):
     F -= sent
     F += d * (transition_sparse(g) @ sent)
     return F, H, S
+
+
+# ----------------------------------------------------------- weighted graphs
+
+def transition_dense_weighted(g, w) -> np.ndarray:
+    """Dense P for a weighted graph: P[j, i] = sum of the weights w_e of the
+    links e = i -> j (each non-empty column sums to one; Section 2.1 allows any
+    such P).  Dangling columns are zero."""
+    n, rp, ci = _csr(g)
+    w = np.asarray(w, dtype=np.float64)
+    P = np.zeros((n, n))
+    for i in range(n):
+        for e in range(rp[i], rp[i + 1]):
+            P[ci[e], i] += w[e]
+    return P
+
+
+def dense_exact_weighted(g, w, d: float, v=None):
+    """(Y, x*) of dense_exact for the weighted P."""
+    n = int(g.n)
+    v = _v(n, v)
+    Y = np.linalg.solve(np.eye(n) - d * transition_dense_weighted(g, w), (1.0 - d) * v)
+    return Y, Y / np.abs(Y).sum()
+
+
+def set_step_weighted(g, w, d: float, theta: float, F, H):
+    """One set step on a weighted graph: S = {i : F_i != 0, |F_i| >= theta},
+    H += F on S, F = 0 on S, F += d P (the fluid sent), P from the weights."""
+    import scipy.sparse as sp
+    n, rp, ci = _csr(g)
+    src = np.repeat(np.arange(n), np.diff(rp))
+    P = sp.csc_matrix((np.asarray(w, dtype=np.float64), (ci.astype(np.int64), src)), shape=(n, n))
+    F = np.array(F, dtype=np.float64)
+    H = np.array(H, dtype=np.float64)
+    S = (F != 0.0) & (np.abs(F) >= theta)
+    sent = np.where(S, F, 0.0)
+    H += sent
+    F -= sent
+    F += d * (P @ sent)
+    return F, H, S

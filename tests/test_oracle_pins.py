@@ -365,3 +365,36 @@ def test_modify_graph_changes_only_the_chosen_rows():
     for i in sorted(set(range(g1.n)) - set(same)):  # new rows: no self-links, no repeats
         row = g1.col_idx[g1.row_ptr[i]:g1.row_ptr[i + 1]]
         assert len(set(row.tolist())) == len(row) and i not in row
+
+
+# ------------------------------------------------------------ weighted P
+
+def test_weighted_closed_form_two_nodes():
+    """Node 0 keeps 0.7 of its pushes on itself and sends 0.3 to node 1, which
+    is dangling: Y0 = (1-d)v0/(1-0.7d), Y1 = (1-d)v1 + 0.3 d Y0."""
+    g = wl.from_edges(2, [0, 0], [0, 1])
+    w = np.array([0.7, 0.3])  # rows sorted by destination: 0 -> 0, 0 -> 1
+    v = np.array([0.25, 0.75])
+    Y, _ = oracle.dense_exact_weighted(g, w, D, v)
+    y0 = (1 - D) * 0.25 / (1 - 0.7 * D)
+    np.testing.assert_allclose(Y, [y0, (1 - D) * 0.75 + 0.3 * D * y0], rtol=1e-14)
+
+
+def test_weighted_with_uniform_weights_is_the_unweighted_limit():
+    g = wl.random_small(60, 300, seed=12, p_dangling=0.2)
+    w = 1.0 / np.repeat(np.diff(g.row_ptr), np.diff(g.row_ptr))
+    np.testing.assert_allclose(oracle.dense_exact_weighted(g, w, D)[1], oracle.dense_exact(g, D)[1],
+                               atol=1e-14)
+
+
+def test_weighted_set_steps_reach_the_weighted_limit():
+    g = wl.random_small(50, 250, seed=13, p_dangling=0.2)
+    w = wl.random_weights(g, seed=14)
+    F, H = oracle.init_state(g.n, D)
+    for _ in range(2000):
+        nf = np.abs(F).sum()
+        if nf < 1e-14:
+            break
+        F, H, _ = oracle.set_step_weighted(g, w, D, nf / g.n, F, H)
+    np.testing.assert_allclose((H + F) / (H + F).sum(), oracle.dense_exact_weighted(g, w, D)[1],
+                               atol=1e-12)

@@ -259,6 +259,17 @@ def paper_scenario(name: str, seed: int = 1) -> Graph:
     return from_edges(n, chosen // n, chosen % n, "paper-" + name)
 
 
+def random_weights(g: Graph, seed: int) -> np.ndarray:
+    """Link weights for g: positive, uniform in (0.05, 1], each non-empty row
+    normalised to sum to one."""
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.05, 1.0, size=g.m)
+    deg = np.diff(g.row_ptr)
+    src = np.repeat(np.arange(g.n), deg)
+    tot = np.bincount(src, weights=w, minlength=g.n)
+    return w / tot[src]
+
+
 def uniform_v(n: int) -> np.ndarray:
     return np.full(n, 1.0 / n)
 
