@@ -139,3 +139,22 @@ def test_cancel_and_validation(di, graphs):
     with pytest.raises(di.DiError):
         srv.submit(7, np.array([1], np.int32))
     srv.close()
+
+
+def test_fp64_server_and_weighted_seed_sets(di, graphs):
+    g = graphs[0]
+    G = di.Graph(g)
+    srv = di.Server(hbm_budget_bytes=2 << 30, max_slots=4, topk=20, precision="fp64")
+    gid = srv.add_graph(G)
+    rng = np.random.default_rng(31)
+    seeds = np.sort(rng.choice(g.n, 12, replace=False)).astype(np.int32)
+    w = rng.random(12)
+    w /= w.sum()
+    r1 = srv.wait(srv.submit(gid, seeds, w=w, d=D, tol=1e-12), 60.0)
+    r2 = srv.wait(srv.submit(gid, seeds, d=D, tol=1e-12), 60.0)
+    srv.close()
+    v = np.zeros(g.n)
+    v[seeds] = w
+    check_topk(r1, oracle.limit(g, D, v, tol=1e-14), 20, 1e-12)
+    check_topk(r2, oracle.limit(g, D, wl.seed_vector(g.n, seeds), tol=1e-14), 20, 1e-12)
+    assert r1["residual_l1"] < 1e-12 and r2["residual_l1"] < 1e-12
