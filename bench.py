@@ -406,6 +406,8 @@ def main():
     ap.add_argument("--no-replay", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="library default knobs instead of di_autotune's choice")
+    ap.add_argument("--section", choices=["ppr", "serve", "update", "replay"],
+                    help="run only this part and print its JSON (profiling runs)")
     ap.add_argument("--tune", metavar="SCHED:C:WLOG:THREADS",
                     help="fixed knobs for the single solve instead of autotuning (profiling runs)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -443,6 +445,13 @@ def main():
     g = wl.recipe(args.workload)
     G = di.Graph(g)
     log("graph n=%d links=%d dangling=%d" % (g.n, g.m, g.n_dangling))
+    if args.section:
+        part = {"ppr": lambda: bench_ppr_batch(di, G, g, args),
+                "serve": lambda: bench_serve(di, args),
+                "update": lambda: bench_update(di, G, g, args),
+                "replay": lambda: bench_paper_replay(di, args)}[args.section]()
+        print(json.dumps({"section": args.section, "result": part}), flush=True)
+        return
 
     # ---- autotuner: the knobs every later solve on this graph uses
     tune_info = None
