@@ -67,8 +67,9 @@ enum {
 enum {
   DI_DEVICE_PTRS = 1u, /* v / x / seeds-weights are device pointers */
   DI_RESUME = 2u,      /* di_solve: start from the state passed in di_opts.state_f/state_h */
-  DI_TIMING = 4u       /* time every launch of the round (or product) kernel with HIP events
+  DI_TIMING = 4u,      /* time every launch of the round (or product) kernel with HIP events
                           on the call's stream: fills kernel_seconds / kernel_launches */
+  DI_TRACE = 8u        /* di_solve: record the set S_r each round takes in opts.trace_sets */
 };
 
 /* threshold schedule families (Section 4.2 threshold variant; Section 4.3 scores) */
@@ -98,6 +99,9 @@ typedef struct di_opts {
   uint32_t pad;
   void* state_f;      /* DI_RESUME: device fluid (float* or double* per precision), in/out */
   double* state_h;    /* DI_RESUME: device history (double*), in/out */
+  uint8_t* trace_sets; /* DI_TRACE: device bytes [trace_rounds][n], zeroed by the caller;
+                          byte (r, i) is set to 1 when round r takes node i */
+  int64_t trace_rounds; /* DI_TRACE: rounds the trace holds (later rounds are not recorded) */
 } di_opts;
 
 typedef struct di_stats {

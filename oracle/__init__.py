@@ -299,3 +299,17 @@ def set_step_weighted(g, w, d: float, theta: float, F, H):
     F -= sent
     F += d * (P @ sent)
     return F, H, S
+
+
+def apply_set(g, d: float, S, F, H):
+    """Diffuse exactly the set S (boolean mask) from (F, H): H += F on S, F = 0
+    on S, F += d P (the fluid sent) -- the set form of the Section 2.2
+    recurrences, for replaying a recorded sequence of sets."""
+    F = np.array(F, dtype=np.float64)
+    H = np.array(H, dtype=np.float64)
+    S = np.asarray(S, dtype=bool)
+    sent = np.where(S, F, 0.0)
+    H += sent
+    F -= sent
+    F += d * (transition_sparse(g) @ sent)
+    return F, H

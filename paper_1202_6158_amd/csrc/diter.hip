@@ -79,6 +79,8 @@ struct DiArgs {
   int64_t max_rounds;
   int weighted;
   int threads;  // round workgroup size (host side: selects the kernel instance)
+  uint8_t* trace;        // [trace_rounds][n] taken sets of a traced solve (NULL: none)
+  int64_t trace_rounds;
 };
 
 // ------------------------------------------------------------ table setup
@@ -501,6 +503,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       Hv[j0 + q] = h[u] + f[u];
       win[q] = 0.0;
       s_state[q] = 2;
+      if (a.trace && r < a.trace_rounds) a.trace[(int64_t)r * a.n + j0 + q] = 1;
       acc[5] += 1.0;
       if (dgs[u] > 0) {
         acc[1] += fabs(f[u]);
@@ -1047,6 +1050,12 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   double* H = resume ? o->state_h : ws->H.as<double>();
   DiArgs<T> a = make_args<T>(g, ws, o->d, o->tol, tp.c, max_rounds, F, H, 1);
   a.threads = tp.threads;
+  if (o->flags & DI_TRACE) {
+    DI_REQUIRE(o->trace_sets != nullptr && o->trace_rounds >= 0,
+               "DI_TRACE needs trace_sets and trace_rounds >= 0");
+    a.trace = o->trace_sets;
+    a.trace_rounds = o->trace_rounds;
+  }
   LaunchTimer lt(s, (o->flags & DI_TIMING) != 0);
   EventTimer timer(s);
   k_init<T><<<dim3(grid_for(g->n, 2048), 1), kBlock, 0, s>>>(a, vdev, resume ? 1 : 0, 0);

@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ------------------------------------------------------------------ constants
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EAGAIN, ECANCELED, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 FP32_FLUID, FP64 = 0, 1
-DEVICE_PTRS, RESUME, TIMING = 1, 2, 4
+DEVICE_PTRS, RESUME, TIMING, TRACE = 1, 2, 4, 8
 SCHED_MEAN, SCHED_OP2, SCHED_OP = 0, 1, 2
 PRECISION = {"fp32": FP32_FLUID, "fp64": FP64, FP32_FLUID: FP32_FLUID, FP64: FP64}
 SCHEDULE = {"mean": SCHED_MEAN, "op2": SCHED_OP2, "op": SCHED_OP}
@@ -56,7 +56,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("d", ctypes.c_double), ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("normalize", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
                 ("tune", ctypes.POINTER(Tune)), ("flags", ctypes.c_uint32), ("pad", ctypes.c_uint32),
-                ("state_f", ctypes.c_void_p), ("state_h", ctypes.c_void_p)]
+                ("state_f", ctypes.c_void_p), ("state_h", ctypes.c_void_p),
+                ("trace_sets", ctypes.c_void_p), ("trace_rounds", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -245,11 +246,12 @@ def _device_vec(v, n):
 
 def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=True,
           max_rounds=0, tune=None, out=None, state=None, stream=None, allow_notconv=False,
-          timing=False):
+          timing=False, trace=None):
     """D-iteration solve on the device.  v: None (uniform), numpy or torch cuda
     float64[n].  Returns (x: torch cuda float64[n], stats dict).  With
     state=(F, H) (torch cuda tensors, F float32/float64 per precision, H
-    float64) the solve resumes from and updates that state."""
+    float64) the solve resumes from and updates that state.  trace: a zeroed
+    torch cuda uint8[rounds, n] tensor that receives the set each round takes."""
     torch = _torch()
     n = graph.n
     x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
@@ -260,6 +262,11 @@ def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=Tr
         o.flags |= RESUME
         o.state_f = state[0].data_ptr()
         o.state_h = state[1].data_ptr()
+    if trace is not None:
+        assert trace.dtype == torch.uint8 and trace.is_cuda and trace.shape[-1] == n
+        o.flags |= TRACE
+        o.trace_sets = trace.data_ptr()
+        o.trace_rounds = trace.shape[0]
     st = Stats()
     rc = _lib.di_solve(graph.handle, _ptr(vd), ctypes.byref(o), _ptr(x), ctypes.byref(st),
                        _stream(stream))
