@@ -220,7 +220,7 @@ typedef struct di_tune_trial {
  * Picks the threshold schedule (Section 4.2 threshold variant, Section 4.3
  * OP / OP2 scores), the threshold factor c and the window size of the binned
  * scatter for this graph by timing trial solves on the device: first every
- * schedule x c in {0.25, 0.5, 1, 2, 4} at the default window, then the best
+ * schedule x c in {0.125, 0.25, 0.5, 1, 2} at the default window, then the best
  * pair at larger and smaller windows, one size at a time in each direction
  * while the time improves, then the winner with 1024-thread workgroups.  Any schedule converges to the same
  * limit (the order independence of Section 2), so only speed is compared.
