@@ -59,15 +59,27 @@ def algorithmic_bytes(n, st, precision):
     return 4 * n * st["rounds"] + 52 * st["nodes_diffused"] + 12 * st["edges_diffused"]
 
 
-def measured_traffic(launches_per_solve):
+def launch_knobs(tune):
+    """(schedule, c, window_log2, threads) of a tune dict, threads 0 read as
+    the library's default of 512."""
+    if not tune:
+        return None
+    return [tune["schedule"], round(float(tune["c"]), 6), int(tune["window_log2"]),
+            int(tune["threads"]) or 512]
+
+
+def measured_traffic(tune):
     """HBM bytes per round-kernel launch from the committed counter summary,
-    or None when absent or taken on other kernel sources."""
+    or None when absent, taken on other kernel sources or at other knobs
+    (the knobs set the work of a launch)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     if t.get("kernel_hash") != kernel_hash():
+        return None
+    if t.get("knobs") != launch_knobs(tune):
         return None
     return (t["fetch_kib_per_dispatch"] + t["write_kib_per_dispatch"]) * 1024.0 / t["copy_factor"]
 
@@ -109,10 +121,11 @@ def copy_calibration(mib=COPY_MIB):
     return mib << 20
 
 
-def summarize_counters(fetch_csv, write_csv, copy_bytes=COPY_MIB << 20):
+def summarize_counters(fetch_csv, write_csv, knobs, copy_bytes=COPY_MIB << 20):
     """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the working round
-    launches from two rocprofv3 --pmc runs, scaled by the same counters on
-    the calibration copy; writes profiles/round_kernel_traffic.json."""
+    launches from two rocprofv3 --pmc runs taken at the given knobs (the
+    --tune string of those runs), scaled by the same counters on the
+    calibration copy; writes profiles/round_kernel_traffic.json."""
     import csv
 
     def per_kernel(path, counter):
@@ -134,7 +147,7 @@ def summarize_counters(fetch_csv, write_csv, copy_bytes=COPY_MIB << 20):
     # the calibration copy reads and writes copy_bytes: its largest dispatch
     cf = max(fc) * 1024.0 / copy_bytes if fc else 1.0
     cw = max(wc) * 1024.0 / copy_bytes if wc else 1.0
-    out = {"kernel_hash": kernel_hash(), "fetch_kib_per_dispatch": fkib / cf * 1.0,
+    out = {"kernel_hash": kernel_hash(), "knobs": knobs, "fetch_kib_per_dispatch": fkib / cf * 1.0,
            "write_kib_per_dispatch": wkib / cw * 1.0, "copy_factor": 1.0,
            "raw": {"fetch_kib": fkib, "write_kib": wkib, "copy_fetch_factor": cf,
                    "copy_write_factor": cw, "dispatches": [len(f), len(w)]}}
@@ -444,7 +457,12 @@ def main():
                     help="print per-kernel durations of the working launches from a trace")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters)
+        if not args.tune:
+            sys.exit("--summarize-counters needs the --tune knobs the counter runs used")
+        sc, c, wl_, th = args.tune.split(":")
+        summarize_counters(*args.summarize_counters,
+                           knobs=launch_knobs({"schedule": sc, "c": float(c),
+                                               "window_log2": int(wl_), "threads": int(th)}))
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
@@ -557,7 +575,7 @@ def main():
         "roofline": {"kernel": "k_round (one D-iteration round)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(launches_per_solve),
+                     "traffic": measured_traffic(tune_info["best"] if tune_info else None),
                      "algorithmic_bytes_per_launch": per_launch_bytes,
                      "avg_launch_us": per_launch_sec * 1e6,
                      "launches_per_solve": launches_per_solve,
