@@ -44,6 +44,24 @@ def test_batch_vectors_match_exact_ppr(di, c1, prec, tol, eps):
         assert _l1(xb[b], xs) <= stats[b]["err_bound_l1"] + eps, b
 
 
+@pytest.mark.parametrize("sched,wlog,threads", [("mean", 8, 1024), ("op", 12, 512),
+                                                ("op2", 13, 1024)])
+def test_batch_launch_shapes(di, c1, sched, wlog, threads):
+    """Batches at other schedules, window sizes and workgroup sizes: every
+    vector within its bound of the exact PPR vector."""
+    g = c1
+    G = di.Graph(g)
+    ptr, seeds = wl.ppr_seed_sets(g.n, 6, 100, seed=13)
+    tune = di.make_tune(sched, 0.5, wlog, threads=threads)
+    x, stats = di.solve_batch(G, ptr, seeds, d=D, tol=1e-11, precision="fp64", tune=tune)
+    xb = x.cpu().numpy()
+    for b in range(6):
+        v = wl.seed_vector(g.n, seeds[ptr[b]:ptr[b + 1]])
+        xs = oracle.limit(g, D, v, tol=1e-14)
+        assert stats[b]["residual_l1"] < 1e-11
+        assert _l1(xb[b], xs) <= stats[b]["err_bound_l1"] + 1e-12, b
+
+
 def test_batch_equals_solo(di, c1):
     g = c1
     G = di.Graph(g)

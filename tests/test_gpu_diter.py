@@ -133,6 +133,24 @@ def test_c1_fp64_limit_parity(di, c1, sched, c):
     assert _l1(x.cpu().numpy(), xs) <= 1e-12
 
 
+@pytest.mark.parametrize("wlog", [8, 10, 12, 14])
+@pytest.mark.parametrize("threads", [512, 1024])
+def test_launch_shapes_limit_parity(di, c1, wlog, threads):
+    """Every window size and both workgroup sizes reach the oracle's limit, in
+    fp64 and with fp32 fluid: 2^8 gives 40 windows with a 16-node tail, and
+    2^14, clamped to 2^13 by the LDS budget, a window of eight 1024-node tiles
+    plus a ragged 1808-node one."""
+    g, Y, xs = c1
+    G = di.Graph(g)
+    tune = di.make_tune("op2", 0.5, wlog, threads=threads)
+    x, st = di.solve(G, d=D, tol=1e-14, precision="fp64", tune=tune)
+    assert _l1(x.cpu().numpy(), xs) <= 1e-12
+    assert abs(st["mass_drift"]) < 1e-12
+    x, st = di.solve(G, d=D, tol=1e-8, precision="fp32", tune=tune)
+    assert st["residual_l1"] < 1e-8
+    assert _l1(x.cpu().numpy(), xs) <= st["err_bound_l1"] + 1e-6
+
+
 def test_c1_fp32_limit_parity(di, c1):
     g, Y, xs = c1
     G = di.Graph(g)
