@@ -68,20 +68,23 @@ def launch_knobs(tune):
             int(tune["threads"]) or 512]
 
 
-def measured_traffic(tune):
-    """HBM bytes per round-kernel launch from the committed counter summary,
-    or None when absent, taken on other kernel sources or at other knobs
-    (the knobs set the work of a launch)."""
+def load_traffic():
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
-        return None
-    if t.get("kernel_hash") != kernel_hash():
-        return None
-    if t.get("knobs") != launch_knobs(tune):
-        return None
-    return (t["fetch_kib_per_dispatch"] + t["write_kib_per_dispatch"]) * 1024.0 / t["copy_factor"]
+        return {}
+    return t if t.get("kernel_hash") == kernel_hash() else {}
+
+
+def measured_traffic(tune):
+    """HBM bytes per round-kernel launch from the committed counter summary,
+    or None when absent, taken on other kernel sources or not taken at these
+    knobs (the knobs set the work of a launch)."""
+    for e in load_traffic().get("entries", []):
+        if e["knobs"] == launch_knobs(tune):
+            return (e["fetch_kib_per_dispatch"] + e["write_kib_per_dispatch"]) * 1024.0
+    return None
 
 
 def cpu_baseline(g, d, tol, budget_s):
@@ -147,13 +150,17 @@ def summarize_counters(fetch_csv, write_csv, knobs, copy_bytes=COPY_MIB << 20):
     # the calibration copy reads and writes copy_bytes: its largest dispatch
     cf = max(fc) * 1024.0 / copy_bytes if fc else 1.0
     cw = max(wc) * 1024.0 / copy_bytes if wc else 1.0
-    out = {"kernel_hash": kernel_hash(), "knobs": knobs, "fetch_kib_per_dispatch": fkib / cf * 1.0,
-           "write_kib_per_dispatch": wkib / cw * 1.0, "copy_factor": 1.0,
-           "raw": {"fetch_kib": fkib, "write_kib": wkib, "copy_fetch_factor": cf,
-                   "copy_write_factor": cw, "dispatches": [len(f), len(w)]}}
+    entry = {"knobs": knobs, "fetch_kib_per_dispatch": fkib / cf,
+             "write_kib_per_dispatch": wkib / cw,
+             "raw": {"fetch_kib": fkib, "write_kib": wkib, "copy_fetch_factor": cf,
+                     "copy_write_factor": cw, "dispatches": [len(f), len(w)]}}
+    # one entry per knob setting, all taken on the current kernel sources
+    entries = [e for e in load_traffic().get("entries", []) if e["knobs"] != knobs]
+    out = {"kernel_hash": kernel_hash(),
+           "entries": sorted(entries + [entry], key=lambda e: [str(k) for k in e["knobs"]])}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
-    print(json.dumps(out))
+    print(json.dumps(entry))
 
 
 def summarize_trace(path):

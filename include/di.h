@@ -220,10 +220,11 @@ typedef struct di_tune_trial {
  * Picks the threshold schedule (Section 4.2 threshold variant, Section 4.3
  * OP / OP2 scores), the threshold factor c and the window size of the binned
  * scatter for this graph by timing trial solves on the device: first every
- * schedule x c in {0.125, 0.25, 0.5, 1, 2} at the default window, then the best
- * pair at larger and smaller windows, one size at a time in each direction
- * while the time improves, then the winner with 1024-thread workgroups.  Any schedule converges to the same
- * limit (the order independence of Section 2), so only speed is compared.
+ * schedule x c in {1/32, 1/16, 1/8, 1/4, 1/2, 1, 2} at the default window,
+ * then the best pair at larger and smaller windows, one size at a time in
+ * each direction while the time improves, then the winner with 1024-thread
+ * workgroups.  Any schedule converges to the same limit (the order
+ * independence of Section 2), so only speed is compared.
  * The default knobs (mean, c = 1) run first; every other candidate gets at
  * most four times their rounds (at least 64, at most opts->max_rounds when
  * set) and is discarded if it does not converge within them.

@@ -105,7 +105,7 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
     }
     // 1. schedule x threshold factor at the default window
     const int scheds[] = {DI_SCHED_MEAN, DI_SCHED_OP2, DI_SCHED_OP};
-    const float cs[] = {0.125f, 0.25f, 0.5f, 1.0f, 2.0f};
+    const float cs[] = {0.03125f, 0.0625f, 0.125f, 0.25f, 0.5f, 1.0f, 2.0f};
     for (int sc : scheds)
       for (float c : cs) {
         if (sc == DI_SCHED_MEAN && c == 1.0f) continue;  // step 0
