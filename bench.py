@@ -96,7 +96,7 @@ def cpu_baseline(g, d, tol, budget_s):
         r = oracle.diter(g, d, tol, order="sweep", c=1.0)
         runs += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or runs >= 20:
+        if el >= budget_s or runs >= 100:
             break
     return {"value": runs / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": "%d full solve(s) of the benchmark graph to ||F||_1 < %g by the oracle's "
@@ -438,7 +438,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--d", type=float, default=0.85)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ppr", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
