@@ -68,20 +68,21 @@ def launch_knobs(tune):
             int(tune["threads"]) or 512]
 
 
-def load_traffic():
+def load_traffic(path=TRAFFIC_FILE):
+    """The counter summary, or {} when absent or taken on other kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return {}
     return t if t.get("kernel_hash") == kernel_hash() else {}
 
 
-def measured_traffic(tune):
+def measured_traffic(tune, path=TRAFFIC_FILE):
     """HBM bytes per round-kernel launch from the committed counter summary,
     or None when absent, taken on other kernel sources or not taken at these
     knobs (the knobs set the work of a launch)."""
-    for e in load_traffic().get("entries", []):
+    for e in load_traffic(path).get("entries", []):
         if e["knobs"] == launch_knobs(tune):
             return (e["fetch_kib_per_dispatch"] + e["write_kib_per_dispatch"]) * 1024.0
     return None
@@ -124,11 +125,13 @@ def copy_calibration(mib=COPY_MIB):
     return mib << 20
 
 
-def summarize_counters(fetch_csv, write_csv, knobs, copy_bytes=COPY_MIB << 20):
+def summarize_counters(fetch_csv, write_csv, knobs, copy_bytes=COPY_MIB << 20,
+                       out_path=TRAFFIC_FILE):
     """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the working round
     launches from two rocprofv3 --pmc runs taken at the given knobs (the
     --tune string of those runs), scaled by the same counters on the
-    calibration copy; writes profiles/round_kernel_traffic.json."""
+    calibration copy; adds or replaces the entry for these knobs in out_path
+    (profiles/round_kernel_traffic.json)."""
     import csv
 
     def per_kernel(path, counter):
@@ -155,12 +158,13 @@ def summarize_counters(fetch_csv, write_csv, knobs, copy_bytes=COPY_MIB << 20):
              "raw": {"fetch_kib": fkib, "write_kib": wkib, "copy_fetch_factor": cf,
                      "copy_write_factor": cw, "dispatches": [len(f), len(w)]}}
     # one entry per knob setting, all taken on the current kernel sources
-    entries = [e for e in load_traffic().get("entries", []) if e["knobs"] != knobs]
+    entries = [e for e in load_traffic(out_path).get("entries", []) if e["knobs"] != knobs]
     out = {"kernel_hash": kernel_hash(),
            "entries": sorted(entries + [entry], key=lambda e: [str(k) for k in e["knobs"]])}
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(entry))
+    return entry
 
 
 def summarize_trace(path):
@@ -457,7 +461,7 @@ def main():
     ap.add_argument("--serve-solo", type=int, default=100)
     ap.add_argument("--serve-hbm-gib", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 256 MiB device copy (counter calibration)")
+                    help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/round_kernel_traffic.json from two --pmc runs")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV",
@@ -476,7 +480,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 
