@@ -20,6 +20,12 @@ Plain, slow, obviously-correct fp64 implementations written from the paper
 * :func:`inject_update` -- the fluid a graph update injects, F' = F + d(P'-P)H
   (updating equation, Section 3.3); :func:`set_step_signed` -- a set step on
   fluid of either sign (|F_i| against the threshold), in numpy.
+* :func:`dense_exact_weighted` / :func:`set_step_weighted` -- the limit and a set
+  step for a weighted P (any column-stochastic P of Section 2.1), in numpy.
+* :func:`apply_set` -- diffusion of a given set, for replaying the sets a solve
+  recorded round by round, in numpy.
+* :func:`limit` -- ``x*`` by :func:`dense_exact` on small graphs, else by
+  :func:`power` run to a tolerance far below the one under test.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It shares no code with the GPU library
