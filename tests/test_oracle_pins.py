@@ -247,6 +247,42 @@ def test_set_step_keeps_theorem1():
     np.testing.assert_allclose(H + F, F0 + D * (P_sparse(g) @ H), rtol=1e-13, atol=1e-18)
 
 
+def test_apply_set_by_hand_and_against_the_threshold_step():
+    """apply_set (numpy) on the hand-worked example, and on random states equal
+    to the C set step when given the threshold set."""
+    g = wl.from_edges(3, [0, 0, 1], [1, 2, 2])
+    a, b, c = 0.5, 0.1, 0.3
+    F, H = oracle.apply_set(g, D, [True, False, True], [a, b, c], [1.0, 2.0, 3.0])
+    np.testing.assert_allclose(F, [0.0, b + D * a / 2, D * a / 2], rtol=1e-15)
+    np.testing.assert_allclose(H, [1.0 + a, 2.0, 3.0 + c], rtol=1e-15)
+    g = wl.random_small(300, 1500, seed=23)
+    rng = np.random.default_rng(3)
+    F0 = rng.uniform(0, 1, g.n) * (rng.uniform(size=g.n) < 0.7)
+    H0 = rng.uniform(0, 1, g.n)
+    theta = 0.5 * F0.mean()
+    Fc, Hc, taken, _ = oracle.set_step(g, D, theta, F0, H0)
+    Fa, Ha = oracle.apply_set(g, D, taken, F0, H0)
+    np.testing.assert_array_equal(Ha, Hc)
+    np.testing.assert_allclose(Fa, Fc, rtol=1e-14, atol=1e-17)
+
+
+def test_apply_set_keeps_theorem1_and_reaches_the_limit():
+    """Any sequence of sets keeps H + F = F_0 + dPH (Theorem 1); sets that keep
+    taking the nodes with fluid reach the exact limit (Theorem 2)."""
+    g = wl.random_small(200, 900, seed=24)
+    F, H = oracle.init_state(g.n, D)
+    F0 = F.copy()
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        F, H = oracle.apply_set(g, D, rng.uniform(size=g.n) < 0.4, F, H)
+        np.testing.assert_allclose(H + F, F0 + D * (P_sparse(g) @ H), rtol=1e-13, atol=1e-18)
+    for _ in range(400):
+        F, H = oracle.apply_set(g, D, F > 0, F, H)
+    assert F.sum() < 1e-14
+    np.testing.assert_allclose((H + F) / (H + F).sum(), oracle.dense_exact(g, D)[1],
+                               rtol=0, atol=1e-13)
+
+
 # --------------------------------------------------- stop rule and orders
 
 @pytest.mark.parametrize("tol", [1e-4, 1e-8])
