@@ -158,3 +158,28 @@ def test_fp64_server_and_weighted_seed_sets(di, graphs):
     check_topk(r1, oracle.limit(g, D, v, tol=1e-14), 20, 1e-12)
     check_topk(r2, oracle.limit(g, D, wl.seed_vector(g.n, seeds), tol=1e-14), 20, 1e-12)
     assert r1["residual_l1"] < 1e-12 and r2["residual_l1"] < 1e-12
+
+
+@pytest.mark.parametrize("sched,c,wlog,threads", [("op2", 0.03125, 8, 1024), ("op", 0.5, 13, 512)])
+def test_server_launch_shapes(di, graphs, sched, c, wlog, threads):
+    """Served results at other schedules, windows (2^8: 118 windows of the
+    30k-node graph; 2^13: four, the last one ragged) and workgroup sizes, vs
+    the exact PPR vectors."""
+    g = graphs[1]
+    G = di.Graph(g)
+    srv = di.Server(hbm_budget_bytes=4 << 30, max_slots=8, topk=30,
+                    tune=di.make_tune(sched, c, wlog, threads=threads))
+    gid = srv.add_graph(G)
+    rng = np.random.default_rng(41)
+    reqs = []
+    for q in range(12):
+        s = int(rng.integers(1, 200))
+        seeds = np.sort(rng.choice(g.n, size=s, replace=False)).astype(np.int32)
+        tol = [1e-6, 1e-8][q % 2]
+        reqs.append((seeds, tol, srv.submit(gid, seeds, d=D, tol=tol)))
+    for seeds, tol, rid in reqs:
+        r = srv.wait(rid, 120.0)
+        assert r is not None and r["status"] == 0
+        assert r["residual_l1"] < tol
+        check_topk(r, oracle.limit(g, D, wl.seed_vector(g.n, seeds), tol=1e-14), 30, 1e-6)
+    srv.close()
