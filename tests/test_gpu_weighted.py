@@ -69,3 +69,57 @@ def test_weighted_batch_matches_dense_limit(di, wg):
         v = wl.seed_vector(g.n, seeds[ptr[b]:ptr[b + 1]])
         xs = oracle.dense_exact_weighted(g, w, D, v)[1]
         assert float(np.abs(x[b].cpu().numpy() - xs).sum()) <= st[b]["err_bound_l1"] + 1e-12
+
+
+def test_weighted_server_matches_dense_limit(di, wg):
+    """Served PPR on the weighted graph: the top-k values within the reported
+    bound of the oracle's dense weighted PPR vector, in rank order."""
+    g, w, _ = wg
+    G = di.Graph(g, w=w)
+    srv = di.Server(hbm_budget_bytes=2 << 30, max_slots=4, topk=20, precision="fp64")
+    gid = srv.add_graph(G)
+    rng = np.random.default_rng(25)
+    reqs = []
+    for s in (1, 7, 60):
+        seeds = np.sort(rng.choice(g.n, s, replace=False)).astype(np.int32)
+        reqs.append((seeds, srv.submit(gid, seeds, d=D, tol=1e-12)))
+    for seeds, rid in reqs:
+        r = srv.wait(rid, 60.0)
+        assert r is not None and r["status"] == 0 and r["residual_l1"] < 1e-12
+        xs = oracle.dense_exact_weighted(g, w, D, wl.seed_vector(g.n, seeds))[1]
+        ids, vals = r["top_ids"], r["top_x"]
+        assert np.all(np.diff(vals) <= 0)
+        assert np.all(np.abs(vals - xs[ids]) <= r["err_bound_l1"] + 1e-12)
+        assert np.sort(xs)[::-1][len(ids) - 1] <= vals[-1] + 2 * (r["err_bound_l1"] + 1e-12)
+    srv.close()
+
+
+def test_weighted_update_of_link_weights(di, wg):
+    """A change of the link weights of 5% of the rows, same links (Section 3.3
+    with P' from the new weights): the injected fluid against the oracle's
+    F + d(P'-P)H on the dense weighted matrices, then the resumed solve
+    against the dense weighted limit of P'."""
+    import torch
+    g, w0, _ = wg
+    rng = np.random.default_rng(26)
+    w1 = w0.copy()
+    deg = np.diff(g.row_ptr)
+    rows = rng.choice(np.flatnonzero(deg > 1), size=int(0.05 * g.n), replace=False)
+    w_new = wl.random_weights(g, seed=27)
+    for i in rows:
+        w1[g.row_ptr[i]:g.row_ptr[i + 1]] = w_new[g.row_ptr[i]:g.row_ptr[i + 1]]
+    G0, G1 = di.Graph(g, w=w0), di.Graph(g, w=w1)
+    F = torch.full((g.n,), (1 - D) / g.n, dtype=torch.float64, device="cuda")
+    H = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    di.solve(G0, d=D, tol=1e-5, precision="fp64", state=(F, H))
+    F0, H0 = F.cpu().numpy(), H.cpu().numpy()
+    di.inject_update(G0, G1, F, H, d=D)
+    P0 = oracle.transition_dense_weighted(g, w0)
+    P1 = oracle.transition_dense_weighted(g, w1)
+    ref = F0 + D * (P1 @ H0) - D * (P0 @ H0)
+    mag = np.abs(F0) + D * (P1 @ np.abs(H0)) + D * (P0 @ np.abs(H0))
+    assert np.all(np.abs(F.cpu().numpy() - ref) <= 8 * 2.0 ** -53 * mag + 1e-300)
+    assert (ref < 0).any()
+    x, st = di.solve(G1, d=D, tol=1e-12, precision="fp64", state=(F, H))
+    xs = oracle.dense_exact_weighted(g, w1, D)[1]
+    assert float(np.abs(x.cpu().numpy() - xs).sum()) <= st["err_bound_l1"] + 1e-12
