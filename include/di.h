@@ -30,7 +30,9 @@
  *    device outputs ready on the stream).
  *  - Vectors `v` and `x` are host pointers unless DI_DEVICE_PTRS is set in the
  *    options' flags, in which case they are device pointers (e.g. the
- *    data_ptr() of a torch tensor on the same device).  Caller-owned.
+ *    data_ptr() of a torch tensor on the same device).  Caller-owned.  A
+ *    device `v` gets the same checks as a host one, by a reduction on the
+ *    call's stream.
  *  - Node ids are 0-based int32; N < 2^31 and nnz < 2^36.
  */
 #ifndef DI_H
@@ -65,7 +67,7 @@ enum {
 
 /* flags */
 enum {
-  DI_DEVICE_PTRS = 1u, /* v / x / seeds-weights are device pointers */
+  DI_DEVICE_PTRS = 1u, /* v and x are device pointers (seed arrays are always host arrays) */
   DI_RESUME = 2u,      /* di_solve: start from the state passed in di_opts.state_f/state_h */
   DI_TIMING = 4u,      /* time every launch of the round (or product) kernel with HIP events
                           on the call's stream: fills kernel_seconds / kernel_launches */

@@ -226,7 +226,10 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
   const bool delta = std::is_same<G, float>::value;
   const int64_t n = g->n;
   const int64_t max_iter = o->max_rounds > 0 ? o->max_rounds : 1000000;
-  if (v && !dev) validate_vector(v, n, "v");
+  if (v) {
+    if (dev) validate_device_vector(v, n, "v", s);
+    else validate_vector(v, n, "v");
+  }
   PowWorkspace ws;
   ws.x0.alloc(n * 8);
   ws.x1.alloc(n * 8);

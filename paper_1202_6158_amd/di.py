@@ -244,19 +244,34 @@ def _device_vec(v, n):
     return v.contiguous()
 
 
+def _host_vec(v, n):
+    """Contiguous float64 host array for v (or None)."""
+    if v is None:
+        return None
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.shape == (n,)
+    return v
+
+
 def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=True,
           max_rounds=0, tune=None, out=None, state=None, stream=None, allow_notconv=False,
-          timing=False, trace=None):
+          timing=False, trace=None, host=False):
     """D-iteration solve on the device.  v: None (uniform), numpy or torch cuda
     float64[n].  Returns (x: torch cuda float64[n], stats dict).  With
     state=(F, H) (torch cuda tensors, F float32/float64 per precision, H
     float64) the solve resumes from and updates that state.  trace: a zeroed
-    torch cuda uint8[rounds, n] tensor that receives the set each round takes."""
+    torch cuda uint8[rounds, n] tensor that receives the set each round takes.
+    host=True passes v and x as host arrays (the library copies them over the
+    bus) and returns x as a numpy array."""
     torch = _torch()
     n = graph.n
-    x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
-    vd = _device_vec(v, n)
-    flags = DEVICE_PTRS | (TIMING if timing else 0)
+    if host:
+        x = out if out is not None else np.empty(n, dtype=np.float64)
+        vd = _host_vec(v, n)
+    else:
+        x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
+        vd = _device_vec(v, n)
+    flags = (0 if host else DEVICE_PTRS) | (TIMING if timing else 0)
     o = make_opts(d, tol, precision, normalize, max_rounds, tune, flags)
     if state is not None:
         o.flags |= RESUME
@@ -277,14 +292,19 @@ def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=Tr
 
 
 def power_solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp64", normalize=True,
-                max_rounds=0, out=None, stream=None, allow_notconv=False, timing=False):
-    """Power-iteration comparator (pull SpMV) on the device."""
+                max_rounds=0, out=None, stream=None, allow_notconv=False, timing=False,
+                host=False):
+    """Power-iteration comparator (pull SpMV) on the device; host as in solve."""
     torch = _torch()
     n = graph.n
-    x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
-    vd = _device_vec(v, n)
+    if host:
+        x = out if out is not None else np.empty(n, dtype=np.float64)
+        vd = _host_vec(v, n)
+    else:
+        x = out if out is not None else torch.empty(n, dtype=torch.float64, device="cuda")
+        vd = _device_vec(v, n)
     o = make_opts(d, tol, precision, normalize, max_rounds, None,
-                  DEVICE_PTRS | (TIMING if timing else 0))
+                  (0 if host else DEVICE_PTRS) | (TIMING if timing else 0))
     st = Stats()
     rc = _lib.di_power_solve(graph.handle, _ptr(vd), ctypes.byref(o), _ptr(x), ctypes.byref(st),
                              _stream(stream))

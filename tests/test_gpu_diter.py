@@ -232,6 +232,46 @@ def test_invalid_vector_rejected(di, c1):
                                    None, None))
 
 
+@pytest.mark.parametrize("bad", ["negative", "nan", "sum"])
+def test_invalid_device_vector_rejected(di, c1, bad):
+    """A device V gets the checks a host V gets: DI_EINVAL, nothing solved."""
+    import torch
+    g, _, _ = c1
+    G = di.Graph(g)
+    v = np.full(g.n, 1.0 / g.n)
+    if bad == "negative":
+        v[17] = -v[17]
+    elif bad == "nan":
+        v[g.n - 1] = np.nan
+    else:
+        v *= 0.5
+    vd = torch.from_numpy(v).cuda()
+    for fn in (di.solve, di.power_solve):
+        with pytest.raises(di.DiError) as e:
+            fn(G, v=vd, d=D, tol=1e-8)
+        assert e.value.status == di.EINVAL
+
+
+def test_host_buffers_match_device_buffers(di, c1):
+    """v and x as host arrays (copied by the library) give the device-pointer
+    results, for the D-iteration and the power iteration."""
+    g, _, _ = c1
+    G = di.Graph(g)
+    rng = np.random.default_rng(9)
+    seeds = np.sort(rng.choice(g.n, 25, replace=False))
+    v = wl.seed_vector(g.n, seeds)
+    xs = oracle.limit(g, D, v, tol=1e-14)
+    for vv in (None, v):
+        xh, sh = di.solve(G, v=vv, d=D, tol=1e-12, precision="fp64", host=True)
+        xd, sd = di.solve(G, v=vv, d=D, tol=1e-12, precision="fp64")
+        assert isinstance(xh, np.ndarray) and abs(sh["rounds"] - sd["rounds"]) <= 1
+        assert _l1(xh, xd.cpu().numpy()) <= 1e-13
+        ph, _ = di.power_solve(G, v=vv, d=D, tol=1e-12, host=True)
+        pd, _ = di.power_solve(G, v=vv, d=D, tol=1e-12)
+        assert _l1(ph, pd.cpu().numpy()) <= 1e-13
+    assert _l1(xh, xs) <= sh["err_bound_l1"] + 1e-12
+
+
 @pytest.fixture(scope="module")
 def c2():
     return wl.recipe("powerlaw-1m")
