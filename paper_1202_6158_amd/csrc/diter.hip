@@ -1034,12 +1034,12 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   const bool resume = (o->flags & DI_RESUME) != 0;
   const int64_t max_rounds = o->max_rounds > 0 ? o->max_rounds : 1000000;
   DI_REQUIRE(!resume || (o->state_f && o->state_h), "DI_RESUME needs state_f and state_h");
-  if (v) {
-    if (dev) validate_device_vector(v, g->n, "v", s);
-    else validate_vector(v, g->n, "v");
-  }
+  if (v && !dev) validate_vector(v, g->n, "v");
   WsGuard guard{g, acquire_workspace(g, o->precision, tp.wlog), s};
   Workspace* ws = guard.ws;
+  // a device v: checked with the flush scratch (cleared again before the flush)
+  if (v && dev)
+    validate_device_vector(v, g->n, "v", ws->flacc.as<double>(), ws->hctl.as<double>(), s);
   const double* vdev = nullptr;
   if (v) {
     if (dev) {

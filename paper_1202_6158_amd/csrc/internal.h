@@ -197,8 +197,11 @@ SlotPool* make_slot_pool(Graph* g, int precision, int capacity, const di_tune* t
 // Validation helpers.
 void validate_d_tol(const di_opts* o);
 void validate_vector(const double* v, int64_t n, const char* what);
-// The same checks on a device vector (one reduction on stream s, then a sync).
-void validate_device_vector(const double* v, int64_t n, const char* what, hipStream_t s);
+// The same checks on a device vector: one reduction on stream s into dscratch
+// (2 device doubles), read back into hscratch (2 pinned host doubles), then a
+// sync of s.
+void validate_device_vector(const double* v, int64_t n, const char* what, double* dscratch,
+                            double* hscratch, hipStream_t s);
 
 // Per-launch HIP event pairs on one stream (DI_TIMING).  Events come from a
 // pool created before the timed region and grown in blocks; launches made

@@ -226,10 +226,7 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
   const bool delta = std::is_same<G, float>::value;
   const int64_t n = g->n;
   const int64_t max_iter = o->max_rounds > 0 ? o->max_rounds : 1000000;
-  if (v) {
-    if (dev) validate_device_vector(v, n, "v", s);
-    else validate_vector(v, n, "v");
-  }
+  if (v && !dev) validate_vector(v, n, "v");
   PowWorkspace ws;
   ws.x0.alloc(n * 8);
   ws.x1.alloc(n * 8);
@@ -237,6 +234,11 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
   ws.xs1.alloc(n * sizeof(G));
   ws.ctl.alloc(sizeof(PowCtl));
   ws.hctl.alloc(sizeof(PowCtl));
+  // a device v: checked with the residual partials of the control block,
+  // which k_pow_init clears afterwards
+  if (v && dev)
+    validate_device_vector(v, n, "v", &ws.ctl.as<PowCtl>()->acc[0][0],
+                           &ws.hctl.as<PowCtl>()->acc[0][0], s);
   const double* vdev = nullptr;
   if (v) {
     if (dev) vdev = v;

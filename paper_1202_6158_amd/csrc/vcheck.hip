@@ -1,7 +1,8 @@
 // Validation of a personalisation vector held in device memory: the checks a
 // host vector gets (every entry finite and non-negative, sum within 1e-9 of
 // one, so that V is a distribution as Section 2.1 requires), made by one
-// reduction on the caller's stream and a read-back of two numbers.
+// reduction on the caller's stream into scratch of the caller's workspace and
+// a read-back of two numbers (no allocation, no device-wide synchronisation).
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -38,17 +39,16 @@ __global__ __launch_bounds__(kBlock) void k_vcheck(const double* __restrict__ v,
 
 }  // namespace
 
-void validate_device_vector(const double* v, int64_t n, const char* what, hipStream_t s) {
-  DevBuf acc;
-  acc.alloc(2 * sizeof(double));
-  k_vcheck_zero<<<1, 64, 0, s>>>(acc.as<double>());
+void validate_device_vector(const double* v, int64_t n, const char* what, double* dscratch,
+                            double* hscratch, hipStream_t s) {
+  k_vcheck_zero<<<1, 64, 0, s>>>(dscratch);
   DI_HIP(hipGetLastError());
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 1024));
-  k_vcheck<<<grid, kBlock, 0, s>>>(v, n, acc.as<double>());
+  k_vcheck<<<grid, kBlock, 0, s>>>(v, n, dscratch);
   DI_HIP(hipGetLastError());
-  double h[2] = {0.0, 0.0};
-  DI_HIP(hipMemcpyAsync(h, acc.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  DI_HIP(hipMemcpyAsync(hscratch, dscratch, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   DI_HIP(hipStreamSynchronize(s));
+  const double h[2] = {hscratch[0], hscratch[1]};
   DI_REQUIRE(h[1] == 0.0, std::string(what) + " has a negative or non-finite entry");
   DI_REQUIRE(std::fabs(h[0] - 1.0) <= 1e-9, std::string(what) + " does not sum to 1");
 }
