@@ -202,14 +202,19 @@ def bench_ppr_batch(di, G, g, args):
     import numpy as np
     import workloads as wl
     ptr, seeds = wl.ppr_seed_sets(g.n, 256, 100, seed=4)
-    tune = None
-    if not args.no_autotune:  # tuned on a separate sample of 32 seed sets
+    tune, fixed = None, None
+    if args.batch_tune:  # fixed knobs (profiling runs)
+        sc, c, wl_, th = args.batch_tune.split(":")
+        fixed = di.make_tune(sc, float(c), int(wl_), threads=int(th))
+        tune = di.tune_dict(fixed)
+    elif not args.no_autotune:  # tuned on a separate sample of 32 seed sets
         sp, ss = wl.ppr_seed_sets(g.n, 32, 100, seed=40)
         best, _ = di.autotune(G, "batch", d=args.d, tol=1e-6, precision="fp32", seed_ptr=sp,
                               seeds=ss)
         tune = di.tune_dict(best)
     try:
-        run = lambda: di.solve_batch(G, ptr, seeds, d=args.d, tol=1e-6, precision="fp32")
+        run = lambda: di.solve_batch(G, ptr, seeds, d=args.d, tol=1e-6, precision="fp32",
+                                     tune=fixed)
         t, outs = time_steps(run, 1, 1)
     except di.DiError as e:
         return {"status": "unavailable", "reason": str(e)}
@@ -222,9 +227,15 @@ def bench_ppr_batch(di, G, g, args):
     import torch
     torch.cuda.synchronize()
     solo = (time.perf_counter() - t1) / 16
+    # the single solve's byte model summed over the vectors, over the whole batch time
+    abytes = float(sum(algorithmic_bytes(g.n, s, "fp32") for s in stats))
     return {"vectors": 256, "tol": 1e-6, "tune": tune, "seconds": t, "vectors_per_s": 256 / t,
             "solo_seconds_per_vector": solo, "speedup_vs_solo": solo * 256 / t,
-            "edges_diffused": int(sum(s["edges_diffused"] for s in stats))}
+            "edges_diffused": int(sum(s["edges_diffused"] for s in stats)),
+            "rounds_max": int(max(s["rounds"] for s in stats)),
+            "rounds_mean": float(np.mean([s["rounds"] for s in stats])),
+            "algorithmic_bytes": abytes, "achieved_gbs": abytes / t / 1e9,
+            "frac_of_hbm_peak": abytes / t / 1e9 / HBM_PEAK_GBS}
 
 
 def bench_update(di, G, g, args):
@@ -454,6 +465,8 @@ def main():
                     help="run only this part and print its JSON (profiling runs)")
     ap.add_argument("--tune", metavar="SCHED:C:WLOG:THREADS",
                     help="fixed knobs for the single solve instead of autotuning (profiling runs)")
+    ap.add_argument("--batch-tune", metavar="SCHED:C:WLOG:THREADS",
+                    help="fixed knobs for the batch instead of autotuning (profiling runs)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)

@@ -197,9 +197,9 @@ SlotPool* make_slot_pool(Graph* g, int precision, int capacity, const di_tune* t
 // Validation helpers.
 void validate_d_tol(const di_opts* o);
 void validate_vector(const double* v, int64_t n, const char* what);
-// The same checks on a device vector: one reduction on stream s into dscratch
-// (2 device doubles), read back into hscratch (2 pinned host doubles), then a
-// sync of s.
+// The same checks on a device vector: reductions on stream s through dscratch
+// (514 device doubles), read back into hscratch (2 pinned host doubles), then
+// a sync of s.
 void validate_device_vector(const double* v, int64_t n, const char* what, double* dscratch,
                             double* hscratch, hipStream_t s);
 
