@@ -33,7 +33,10 @@
  *    data_ptr() of a torch tensor on the same device).  Caller-owned.  A
  *    device `v` gets the same checks as a host one, by a reduction on the
  *    call's stream.
- *  - Node ids are 0-based int32; N < 2^31 and nnz < 2^36.
+ *  - Node ids are 0-based int32; N < 2^31 and nnz < 2^36.  Solves need the
+ *    binned scatter's windows to fit: at most 16384 windows of 2^13 nodes, so
+ *    N <= 134,217,728 (DI_EINVAL beyond; graphs above ~25M nodes keep the
+ *    per-window tables in global memory, see di_tune.tables).
  */
 #ifndef DI_H
 #define DI_H
@@ -88,6 +91,9 @@ typedef struct di_tune {
   int32_t window_log2; /* destination window of the binned scatter: 2^k nodes (8..14) */
   int32_t check_every; /* rounds between host checks of the device done flag (0 = adaptive) */
   int32_t threads;     /* round workgroup size: 512 (default, 0) or 1024 (more loads in flight) */
+  int32_t tables;      /* per-window segment tables of the binned scatter: 0 = in LDS when they
+                          fit, else in global memory (graphs above ~25M nodes); 1 = LDS only;
+                          2 = global memory (runs 1024-thread workgroups) */
 } di_tune;
 
 typedef struct di_opts {

@@ -75,7 +75,7 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
       DI_REQUIRE(B >= 1 && seed_ptr != nullptr && seeds != nullptr,
                  "DI_TUNE_BATCH needs B >= 1 seed sets");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int w0 = window_log2_for(g->n, 0);
+    const int w0 = window_log2_for(g->n, 0, 0, nullptr);
     DI_REQUIRE(w0 > 0, "graph has too many nodes for the window tables");
 
     std::vector<Trial> done;
@@ -119,7 +119,7 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
       std::vector<int> tried{w0};
       for (int dir : {-1, 1}) {
         for (int wl = w0 + dir;; wl += dir) {
-          const int eff = window_log2_for(g->n, wl);
+          const int eff = window_log2_for(g->n, wl, 0, nullptr);
           if (eff <= 0 || std::find(tried.begin(), tried.end(), eff) != tried.end()) break;
           tried.push_back(eff);
           const Trial t = run(win.tune.schedule, win.tune.c, eff);

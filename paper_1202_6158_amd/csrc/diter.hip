@@ -37,6 +37,7 @@ namespace di {
 
 struct Workspace {
   int precision = 0, wlog = 0, nb = 0, nvec = 0;
+  bool gt = false;  // segment tables read from global memory (not staged in LDS)
   int64_t n = 0, m = 0;
   DevBuf F, H, v, x, bstart, ctl, flacc, active;
   DevBuf pairs[2], cnt[2], slots;
@@ -79,6 +80,7 @@ struct DiArgs {
   int64_t max_rounds;
   int weighted;
   int threads;  // round workgroup size (host side: selects the kernel instance)
+  int gt;       // segment tables in global memory (host side: selects the kernel instance)
   uint8_t* trace;        // [trace_rounds][n] taken sets of a traced solve (NULL: none)
   int64_t trace_rounds;
 };
@@ -261,7 +263,11 @@ constexpr int kSuper = 1024;        // window nodes decided and expanded per pas
 
 // One round; mode 1 forces a fold-only launch (after an explicit single round).
 // NT threads per workgroup (512 or 1024: more loads in flight per window).
-template <typename T, int SCHED, int NT>
+// GT: the per-window segment tables (record bases, capacities, fold offsets)
+// are read from global memory where they are used instead of being staged in
+// LDS, so that graphs with many windows fit (only the record counters and
+// ranks stay in LDS).
+template <typename T, int SCHED, int NT, bool GT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_round(DiArgs<T> a, int r,
                                                                                   int mode) {
   constexpr int kRT = NT;
@@ -281,13 +287,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   extern __shared__ __align__(16) unsigned char smem[];
   const int W = 1 << a.wlog;
   const int nb = a.nb;
-  double* win = reinterpret_cast<double*>(smem);             // [W]
-  int64_t* s_base = reinterpret_cast<int64_t*>(win + W);      // [nb]
-  int32_t* s_pre = reinterpret_cast<int32_t*>(s_base + nb);   // [nb+1] fold prefix, then ranks
-  int32_t* s_soff = s_pre + (nb + 1);                         // [nb]
-  int32_t* s_cap = s_soff + nb;                               // [nb]
+  double* win = reinterpret_cast<double*>(smem);  // [W]
+  int64_t* s_base = nullptr;                       // [nb] record base per destination (not GT)
+  int32_t* s_pre;                                  // [nb+1] fold prefix, then ranks
+  int32_t* s_soff = nullptr;                       // [nb] fold offsets per source (not GT)
+  int32_t* s_cap = nullptr;                        // [nb] capacity per destination (not GT)
   // per node of the window: 0 not taken, 1 taken and not yet expanded, 2 expanded
-  uint8_t* s_state = reinterpret_cast<uint8_t*>(s_cap + nb);  // [W]
+  uint8_t* s_state;  // [W]
+  if constexpr (GT) {
+    s_pre = reinterpret_cast<int32_t*>(win + W);
+    s_state = reinterpret_cast<uint8_t*>(s_pre + (nb + 1));
+  } else {
+    s_base = reinterpret_cast<int64_t*>(win + W);
+    s_pre = reinterpret_cast<int32_t*>(s_base + nb);
+    s_soff = s_pre + (nb + 1);
+    s_cap = s_soff + nb;
+    s_state = reinterpret_cast<uint8_t*>(s_cap + nb);
+  }
   __shared__ int32_t s_beo[kSuper + 1];
   __shared__ int64_t s_brow[kSuper];
   __shared__ double s_bsh[kSuper];
@@ -323,12 +339,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   int32_t c_own = 0, o_own = 0, cap_own = 0;  // first pass over windows (nb <= kRT usually)
   int64_t base_own = 0;
   if (tid < nb) {
-    if (r >= 1) {
-      c_own = cnt_in[tid];
-      o_own = a.soff[(int64_t)b * nb + tid];
+    if (r >= 1) c_own = cnt_in[tid];
+    if constexpr (!GT) {
+      if (r >= 1) o_own = a.soff[(int64_t)b * nb + tid];
+      base_own = a.bstart[tid] + a.soffT[(int64_t)b * nb + tid];
+      cap_own = a.capT[(int64_t)b * nb + tid];
     }
-    base_own = a.bstart[tid] + a.soffT[(int64_t)b * nb + tid];
-    cap_own = a.capT[(int64_t)b * nb + tid];
   }
   // Launch r itself records stop_round = r-1; an earlier stop ends this launch.
   if (sr >= 0 && sr < r - 1) return;
@@ -383,19 +399,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   for (int q = tid + kWinPer * kRT; q < wn; q += kRT) win[q] = (double)Fv[j0 + q];
   if (tid < nb) {
     s_pre[tid] = c_own;
-    s_soff[tid] = o_own;
-    s_base[tid] = base_own;
-    s_cap[tid] = cap_own;
+    if constexpr (!GT) {
+      s_soff[tid] = o_own;
+      s_base[tid] = base_own;
+      s_cap[tid] = cap_own;
+    }
   }
   for (int s = tid + kRT; s < nb; s += kRT) {
-    if (r >= 1) {
-      s_pre[s] = cnt_in[s];
-      s_soff[s] = a.soff[(int64_t)b * nb + s];
-    } else {
-      s_pre[s] = 0;
+    s_pre[s] = r >= 1 ? cnt_in[s] : 0;
+    if constexpr (!GT) {
+      if (r >= 1) s_soff[s] = a.soff[(int64_t)b * nb + s];
+      s_base[s] = a.bstart[s] + a.soffT[(int64_t)b * nb + s];
+      s_cap[s] = a.capT[(int64_t)b * nb + s];
     }
-    s_base[s] = a.bstart[s] + a.soffT[(int64_t)b * nb + s];
-    s_cap[s] = a.capT[(int64_t)b * nb + s];
   }
   __syncthreads();
   long long total = 0;  // records addressed to this window in round r-1
@@ -404,12 +420,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   if (total > 0) {
     const PairT<T>* pr = a.pairs[(r - 1) & 1] + (int64_t)vb * a.mrec;
     const int64_t base = a.bstart[b];
+    // offset of segment (s -> this window) within the window's record region
+    auto seg_off = [&](int s) -> int64_t {
+      if constexpr (GT) return a.soff[(int64_t)b * nb + s];
+      else return s_soff[s];
+    };
     // Each thread takes kRun consecutive records: one search for the segment
     // of the first, then a forward walk over the segment boundaries.
     for (long long i0 = (long long)tid * kRun; i0 < total; i0 += (long long)kRT * kRun) {
       int s = upper_idx(s_pre, nb, i0);
       long long nxt = s + 1 < nb ? s_pre[s + 1] : total;
-      int64_t sb = base + s_soff[s] - s_pre[s];  // record index = sb + i within segment s
+      int64_t sb = base + seg_off(s) - s_pre[s];  // record index = sb + i within segment s
       int64_t idx[kRun];
 #pragma unroll
       for (int u = 0; u < kRun; ++u) {
@@ -419,7 +440,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
           while (i >= nxt) {
             ++s;
             nxt = s + 1 < nb ? s_pre[s + 1] : total;
-            sb = base + s_soff[s] - s_pre[s];
+            sb = base + seg_off(s) - s_pre[s];
           }
           idx[u] = sb + i;
         }
@@ -572,13 +593,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
           local_push = 1;
           continue;
         }
+        int cap;
+        int64_t wbase;  // first record of segment (this window -> w)
+        if constexpr (GT) {
+          const int64_t q = (int64_t)b * nb + w;
+          cap = a.capT[q];
+          wbase = a.bstart[w] + a.soffT[q];
+        } else {
+          cap = s_cap[w];
+          wbase = s_base[w];
+        }
         const int rank = atomicAdd(&s_pre[w], 1);
-        if (rank < s_cap[w]) {
+        if (rank < cap) {
           PairT<T> pr;
           memset(&pr, 0, sizeof(pr));
           pr.loc = dst[u] & wmask;
           pr.val = (T)v[u];
-          out[s_base[w] + rank] = pr;
+          out[wbase + rank] = pr;
         } else {
           atomicOr(&ctl->err, 2);
         }
@@ -588,7 +619,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     __syncthreads();
   }
   for (int w = tid; w < nb; w += kRT)
-    if (s_pre[w] > 0) cnt_out[(int64_t)w * nb + b] = min(s_pre[w], s_cap[w]);
+    if (s_pre[w] > 0) {
+      int cap;
+      if constexpr (GT) cap = a.capT[(int64_t)b * nb + w];
+      else cap = s_cap[w];
+      cnt_out[(int64_t)w * nb + b] = min(s_pre[w], cap);
+    }
   for (int q = tid; q < wn; q += kRT) Fv[j0 + q] = (T)win[q];
 
   // 4. This window's sums, added into its slot.
@@ -683,7 +719,7 @@ static int64_t bytes_per_vector(int64_t n, int64_t m, int nb, int precision) {
 }
 
 // Workspace for nvec vectors of window 2^wlog (single solves use nvec = 1).
-static Workspace* make_workspace(Graph* g, int precision, int wlog, int nvec) {
+static Workspace* make_workspace(Graph* g, int precision, int wlog, int nvec, bool gt) {
   auto* ws = new Workspace();
   try {
     const int64_t n = g->n, m = g->m, mrec = std::max<int64_t>(m, 1);
@@ -692,6 +728,7 @@ static Workspace* make_workspace(Graph* g, int precision, int wlog, int nvec) {
     const int64_t nb2 = (int64_t)nb * nb;
     ws->precision = precision;
     ws->wlog = wlog;
+    ws->gt = gt;
     ws->nb = nb;
     ws->nvec = nvec;
     ws->n = n;
@@ -745,27 +782,28 @@ static Workspace* make_workspace(Graph* g, int precision, int wlog, int nvec) {
   return ws;
 }
 
-Workspace* acquire_workspace(Graph* g, int precision, int wlog) {
+Workspace* acquire_workspace(Graph* g, int precision, int wlog, bool gt) {
   {
     std::lock_guard<std::mutex> lk(g->ws_mu);
     for (size_t i = 0; i < g->ws_free.size(); ++i) {
       Workspace* ws = g->ws_free[i];
-      if (ws->precision == precision && ws->wlog == wlog && ws->nvec == 1) {
+      if (ws->precision == precision && ws->wlog == wlog && ws->gt == gt && ws->nvec == 1) {
         g->ws_free.erase(g->ws_free.begin() + i);
         return ws;
       }
     }
   }
-  return make_workspace(g, precision, wlog, 1);
+  return make_workspace(g, precision, wlog, 1, gt);
 }
 
 // A workspace for at least nvec vectors (batches); reuses a cached one.
-static Workspace* acquire_batch_workspace(Graph* g, int precision, int wlog, int nvec) {
+static Workspace* acquire_batch_workspace(Graph* g, int precision, int wlog, bool gt, int nvec) {
   {
     std::lock_guard<std::mutex> lk(g->ws_mu);
     for (size_t i = 0; i < g->ws_free.size(); ++i) {
       Workspace* ws = g->ws_free[i];
-      if (ws->precision == precision && ws->wlog == wlog && ws->nvec >= nvec && ws->nvec > 1) {
+      if (ws->precision == precision && ws->wlog == wlog && ws->gt == gt && ws->nvec >= nvec &&
+          ws->nvec > 1) {
         g->ws_free.erase(g->ws_free.begin() + i);
         return ws;
       }
@@ -780,7 +818,7 @@ static Workspace* acquire_batch_workspace(Graph* g, int precision, int wlog, int
       }
     }
   }
-  return make_workspace(g, precision, wlog, nvec);
+  return make_workspace(g, precision, wlog, nvec, gt);
 }
 
 void release_workspace(Graph* g, Workspace* ws) {
@@ -838,6 +876,7 @@ static DiArgs<T> make_args(const Graph* g, Workspace* ws, double d, double tol, 
   a.active = ws->active.as<uint8_t>();
   a.ctl = ws->ctl.as<Ctl>();
   a.flacc = ws->flacc.as<double>();
+  a.gt = ws->gt ? 1 : 0;
   a.nvec = nvec;
   a.d = d;
   a.tol = tol;
@@ -852,19 +891,19 @@ static int grid_for(int64_t n, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
 }
 
-template <typename T, int SCHED, int NT>
+template <typename T, int SCHED, int NT, bool GT = false>
 static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, LaunchTimer* lt) {
-  const size_t smem = round_lds_bytes(a.wlog, a.nb);
+  const size_t smem = round_lds_bytes(a.wlog, a.nb, GT);
   // Dynamic LDS may use what the static part leaves of the workgroup limit
   // (set once per kernel instance; thread-safe initialisation).
   static const size_t dyn_limit = [] {
     hipFuncAttributes fa;
-    DI_HIP(hipFuncGetAttributes(&fa, (const void*)k_round<T, SCHED, NT>));
+    DI_HIP(hipFuncGetAttributes(&fa, (const void*)k_round<T, SCHED, NT, GT>));
     int dev = 0, lim = 0;
     DI_HIP(hipGetDevice(&dev));
     DI_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t dl = (size_t)lim - fa.sharedSizeBytes;
-    DI_HIP(hipFuncSetAttribute((const void*)k_round<T, SCHED, NT>,
+    DI_HIP(hipFuncSetAttribute((const void*)k_round<T, SCHED, NT, GT>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl));
     return dl;
   }();
@@ -874,9 +913,10 @@ static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, L
     // The runtime stamps the kernel's own begin/end into the event pair.
     hipEvent_t e0, e1;
     lt->next(&e0, &e1);
-    hipExtLaunchKernelGGL(k_round<T, SCHED, NT>, grid, dim3(NT), smem, s, e0, e1, 0, a, r, mode);
+    hipExtLaunchKernelGGL(k_round<T, SCHED, NT, GT>, grid, dim3(NT), smem, s, e0, e1, 0, a, r,
+                          mode);
   } else {
-    k_round<T, SCHED, NT><<<grid, NT, smem, s>>>(a, r, mode);
+    k_round<T, SCHED, NT, GT><<<grid, NT, smem, s>>>(a, r, mode);
   }
   DI_HIP(hipGetLastError());
 }
@@ -884,6 +924,20 @@ static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, L
 template <typename T>
 static void launch_round(const DiArgs<T>& a, int sched, int r, int mode, hipStream_t s,
                          LaunchTimer* lt = nullptr) {
+  if (a.gt) {  // segment tables in global memory: 1024-thread instances only
+    switch (sched) {
+      case DI_SCHED_OP2:
+        launch_round_t<T, DI_SCHED_OP2, 1024, true>(a, r, mode, s, lt);
+        break;
+      case DI_SCHED_OP:
+        launch_round_t<T, DI_SCHED_OP, 1024, true>(a, r, mode, s, lt);
+        break;
+      default:
+        launch_round_t<T, DI_SCHED_MEAN, 1024, true>(a, r, mode, s, lt);
+        break;
+    }
+    return;
+  }
   switch (sched) {
     case DI_SCHED_OP2:
       if (a.threads == 1024) launch_round_t<T, DI_SCHED_OP2, 1024>(a, r, mode, s, lt);
@@ -999,6 +1053,7 @@ static di_status status_of(const Ctl& h) {
 
 struct TuneParams {
   int sched, wlog, check_every, threads;
+  bool gt;
   double c;
 };
 
@@ -1018,11 +1073,15 @@ static TuneParams tune_params(Graph* g, const di_tune* tn, int mode, int precisi
   p.sched = tn ? tn->schedule : DI_SCHED_MEAN;
   DI_REQUIRE(p.sched >= 0 && p.sched <= 2, "unknown schedule");
   p.c = (tn && tn->c > 0.f) ? (double)tn->c : 1.0;
-  p.wlog = window_log2_for(g->n, tn ? tn->window_log2 : 0);
+  const int tables = tn ? tn->tables : 0;
+  DI_REQUIRE(tables >= 0 && tables <= 2, "tables must be 0, 1 or 2");
+  p.gt = false;
+  p.wlog = window_log2_for(g->n, tn ? tn->window_log2 : 0, tables, &p.gt);
   DI_REQUIRE(p.wlog > 0, "graph has too many nodes for the window tables");
   p.check_every = tn ? std::max(0, tn->check_every) : 0;
   p.threads = tn && tn->threads ? tn->threads : kRoundThreads;
   DI_REQUIRE(p.threads == 512 || p.threads == 1024, "threads must be 0, 512 or 1024");
+  if (p.gt) p.threads = 1024;  // the only instance with tables in global memory
   return p;
 }
 
@@ -1035,7 +1094,7 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   const int64_t max_rounds = o->max_rounds > 0 ? o->max_rounds : 1000000;
   DI_REQUIRE(!resume || (o->state_f && o->state_h), "DI_RESUME needs state_f and state_h");
   if (v && !dev) validate_vector(v, g->n, "v");
-  WsGuard guard{g, acquire_workspace(g, o->precision, tp.wlog), s};
+  WsGuard guard{g, acquire_workspace(g, o->precision, tp.wlog, tp.gt), s};
   Workspace* ws = guard.ws;
   // a device v: checked with the flush scratch (cleared again before the flush)
   if (v && dev)
@@ -1117,7 +1176,8 @@ static di_status batch_impl(Graph* g, int32_t B, const int64_t* seed_ptr, const 
   const int nb = (int)((n + (1ll << tp.wlog) - 1) >> tp.wlog);
   const int64_t per = bytes_per_vector(n, g->m, nb, o->precision);
   int group = (int)std::max<int64_t>(1, std::min<int64_t>(B, (int64_t)(0.8 * (double)free_b) / per));
-  WsGuard guard{g, acquire_batch_workspace(g, o->precision, tp.wlog, std::max(group, 2)), s};
+  WsGuard guard{g, acquire_batch_workspace(g, o->precision, tp.wlog, tp.gt, std::max(group, 2)),
+                s};
   Workspace* ws = guard.ws;
   group = std::min(group, ws->nvec);
   DevBuf d_ptr, d_seeds, d_w, d_x;
@@ -1165,10 +1225,12 @@ static di_status batch_impl(Graph* g, int32_t B, const int64_t* seed_ptr, const 
 template <typename T>
 static void round_impl(Graph* g, double d, double theta, T* F, double* H, int64_t* tn,
                        int64_t* te, hipStream_t s) {
-  const int wlog = window_log2_for(g->n, 0);
+  bool gt = false;
+  const int wlog = window_log2_for(g->n, 0, 0, &gt);
   DI_REQUIRE(wlog > 0, "graph has too many nodes for the window tables");
   WsGuard guard{g,
-                acquire_workspace(g, std::is_same<T, double>::value ? DI_FP64 : DI_FP32_FLUID, wlog),
+                acquire_workspace(g, std::is_same<T, double>::value ? DI_FP64 : DI_FP32_FLUID, wlog,
+                                  gt),
                 s};
   Workspace* ws = guard.ws;
   DiArgs<T> a = make_args<T>(g, ws, d, 0.0, 1.0, (int64_t)1 << 40, F, H, 1);
@@ -1253,7 +1315,8 @@ __global__ __launch_bounds__(kBlock) void k_topk_collect(DiArgs<T> a, const uint
 // ---------------------------------------------------------- serving engine
 
 int64_t slot_bytes(const Graph* g, int precision) {
-  const int wlog = window_log2_for(g->n, 0);
+  const int wlog = window_log2_for(g->n, 0, 0, nullptr);
+  DI_REQUIRE(wlog > 0, "graph has too many nodes for the window tables");
   const int nb = (int)((g->n + (1ll << wlog) - 1) >> wlog);
   return bytes_per_vector(g->n, g->m, nb, precision);
 }
@@ -1263,7 +1326,7 @@ class SlotPoolT : public SlotPool {
  public:
   SlotPoolT(Graph* g, int precision, int capacity, const di_tune* tune) : g_(g), cap_(capacity) {
     tp_ = tune_params(g, tune, DI_TUNE_BATCH, precision);
-    ws_ = make_workspace(g, precision, tp_.wlog, capacity);
+    ws_ = make_workspace(g, precision, tp_.wlog, capacity, tp_.gt);
     round_.assign(capacity, 0);
     d_.assign(capacity, 0.85);
     tol_.assign(capacity, 1e-6);

@@ -24,23 +24,34 @@ Graph::~Graph() {
   for (Workspace* ws : ws_free) destroy_workspace(ws);
 }
 
-size_t round_lds_bytes(int wlog, int nb) {
-  return ((size_t)9 << wlog) + (size_t)20 * nb + 16;
+size_t round_lds_bytes(int wlog, int nb, bool global_tables) {
+  // fp64 window and a state byte per node; per window either the four segment
+  // tables (base, count prefix / rank, offset, capacity: 20 bytes) or only the
+  // count prefix / rank (4 bytes)
+  return ((size_t)9 << wlog) + (size_t)(global_tables ? 4 : 20) * (nb + 1) + 16;
 }
 
-int window_log2_for(int64_t n, int requested) {
-  constexpr size_t kLdsBudget = 136 * 1024;  // 160 KiB minus the round kernel's static LDS (21 KiB)
-  int k = 8;
+int window_log2_for(int64_t n, int requested, int tables, bool* global_tables) {
+  constexpr size_t kLdsBudget = 136 * 1024;  // 160 KiB minus the round kernel's static LDS (22 KiB)
+  int k0 = 8;
   if (requested >= 8) {
-    k = std::min(requested, 14);
+    k0 = std::min(requested, 14);
   } else {
-    while (k < 14 && (n >> k) > 512) ++k;
+    while (k0 < 14 && (n >> k0) > 512) ++k0;
   }
-  auto nb_of = [&](int kk) { return (int)((n + (1ll << kk) - 1) >> kk); };
-  while (k > 8 && round_lds_bytes(k, nb_of(k)) > kLdsBudget) --k;
-  while (k < 14 && nb_of(k) > kMaxBuckets) ++k;
-  if (nb_of(k) > kMaxBuckets || round_lds_bytes(k, nb_of(k)) > kLdsBudget) return -1;
-  return k;
+  auto nb_of = [&](int kk) { return (int)std::min<int64_t>((n + (1ll << kk) - 1) >> kk, 1 << 30); };
+  for (const bool gt : {false, true}) {
+    if ((gt && tables == 1) || (!gt && tables == 2)) continue;
+    const int maxb = gt ? kMaxBucketsGlobal : kMaxBuckets;
+    int k = k0;
+    while (k > 8 && round_lds_bytes(k, nb_of(k), gt) > kLdsBudget) --k;
+    while (k < 14 && nb_of(k) > maxb) ++k;
+    if (nb_of(k) <= maxb && round_lds_bytes(k, nb_of(k), gt) <= kLdsBudget) {
+      if (global_tables) *global_tables = gt;
+      return k;
+    }
+  }
+  return -1;
 }
 
 void validate_d_tol(const di_opts* o) {

@@ -105,7 +105,8 @@ struct PinnedBuf {
 constexpr int kBlock = 256;        // threads per workgroup of the streaming kernels
 constexpr int kRoundThreads = 512;   // threads per D-iteration round workgroup
 constexpr int64_t kMaxNnz = 1ll << 36;  // links per graph
-constexpr int kMaxBuckets = 4096;  // destination windows per solve
+constexpr int kMaxBuckets = 4096;  // destination windows per solve, tables in LDS
+constexpr int kMaxBucketsGlobal = 16384;  // the same, tables read from global memory
 constexpr int kPullRows = 256;     // rows per pull block (one per thread)
 constexpr int kPullNnz = 2048;     // staged in-links per pull block
 
@@ -141,13 +142,17 @@ struct Graph {
 
 // Window size (log2 nodes) of the binned scatter for a graph of n nodes: about
 // 512 windows, the round kernel's LDS (fp64 window + per-window tables) within
-// the workgroup limit, at most kMaxBuckets windows (-1 if impossible).
-int window_log2_for(int64_t n, int requested);
+// the workgroup limit, at most kMaxBuckets windows.  When no size fits (large
+// graphs), or when tables == 2, the per-window segment tables stay in global
+// memory and only the record counters sit in LDS (at most kMaxBucketsGlobal
+// windows); tables == 1 forbids that.  *global_tables reports the choice;
+// -1 if no size fits.
+int window_log2_for(int64_t n, int requested, int tables, bool* global_tables);
 // LDS bytes of the round kernel's dynamic part for window 2^wlog and nb windows.
-size_t round_lds_bytes(int wlog, int nb);
+size_t round_lds_bytes(int wlog, int nb, bool global_tables);
 
 // Workspaces (defined in diter.hip).
-Workspace* acquire_workspace(Graph* g, int precision, int wlog);
+Workspace* acquire_workspace(Graph* g, int precision, int wlog, bool global_tables);
 void release_workspace(Graph* g, Workspace* ws);
 void destroy_workspace(Workspace* ws);
 

@@ -44,7 +44,7 @@ class DiError(RuntimeError):
 class Tune(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("c", ctypes.c_float),
                 ("window_log2", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("threads", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("tables", ctypes.c_int32)]
 
 
 class TuneTrial(ctypes.Structure):
@@ -175,9 +175,13 @@ def _ptr(a):
     return ctypes.c_void_p(a.data_ptr())
 
 
-def make_tune(schedule="mean", c=1.0, window_log2=0, check_every=0, threads=0) -> Tune:
+TABLES = {"auto": 0, "lds": 1, "global": 2}
+
+
+def make_tune(schedule="mean", c=1.0, window_log2=0, check_every=0, threads=0,
+              tables="auto") -> Tune:
     return Tune(SCHEDULE.get(schedule, schedule), float(c), int(window_log2), int(check_every),
-                int(threads))
+                int(threads), TABLES.get(tables, tables))
 
 
 def make_opts(d=0.85, tol=1e-8, precision="fp32", normalize=True, max_rounds=0, tune=None,
@@ -363,7 +367,8 @@ _SCHED_NAME = {v: k for k, v in SCHEDULE.items()}
 def tune_dict(t: Tune) -> dict:
     return {"schedule": _SCHED_NAME.get(t.schedule, t.schedule), "c": float(t.c),
             "window_log2": int(t.window_log2), "check_every": int(t.check_every),
-            "threads": int(t.threads)}
+            "threads": int(t.threads),
+            "tables": {v: k for k, v in TABLES.items()}.get(int(t.tables), int(t.tables))}
 
 
 def autotune(graph: Graph, mode="solve", d=0.85, tol=1e-8, precision="fp32", seed_ptr=None,
