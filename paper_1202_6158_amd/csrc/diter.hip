@@ -42,7 +42,15 @@ struct Workspace {
   DevBuf F, H, v, x, bstart, ctl, flacc, active;
   DevBuf pairs[2], cnt[2], slots;
   DevBuf soff, soffT, capT;  // nb x nb segment tables
-  PinnedBuf hctl;
+  PinnedBuf hctl, hctl2;     // host copies of the control blocks (two in flight while polling)
+  hipEvent_t ev[2] = {nullptr, nullptr};  // completion of those copies
+  Workspace() = default;
+  Workspace(const Workspace&) = delete;
+  Workspace& operator=(const Workspace&) = delete;
+  ~Workspace() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 template <typename T>
@@ -752,6 +760,8 @@ static Workspace* make_workspace(Graph* g, int precision, int wlog, int nvec, bo
     ws->soffT.alloc(nb2 * 4);
     ws->capT.alloc(nb2 * 4);
     ws->hctl.alloc(nvec * sizeof(Ctl));
+    ws->hctl2.alloc(nvec * sizeof(Ctl));
+    for (hipEvent_t& e : ws->ev) DI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     DevBuf E, err;
     E.alloc(nb2 * 4);
     err.alloc(sizeof(int));
@@ -961,18 +971,34 @@ static void read_ctl(Workspace* ws, int nvec, hipStream_t s) {
 
 // Launches rounds until every vector's launch has recorded its stop (that
 // launch also folds the last pushes, so (F, H) is again a state of the
-// recurrences).
+// recurrences).  Rounds go out in chunks, each followed by an asynchronous
+// copy of the control blocks; while the host waits for one chunk's copy the
+// next chunk is already queued, so the device never idles on the host.  Chunk
+// sizes follow the observed per-round decay of ||F||_1; rounds launched after
+// the stop return at once.
 template <typename T>
 static void run_rounds(const DiArgs<T>& a, Workspace* ws, int sched, int check_every,
                        hipStream_t s, LaunchTimer* lt) {
-  Ctl* h = ws->hctl.as<Ctl>();
+  Ctl* const hb[2] = {ws->hctl.as<Ctl>(), ws->hctl2.as<Ctl>()};
+  const size_t cbytes = (size_t)a.nvec * sizeof(Ctl);
   int r = 0;
-  int chunk = check_every > 0 ? check_every : 8;
+  int obs[2] = {0, 0};  // rounds launched before each buffer's copy
+  auto launch_chunk = [&](int k, int slot) {
+    for (int i = 0; i < k; ++i) launch_round(a, sched, r++, 0, s, lt);
+    DI_HIP(hipMemcpyAsync(hb[slot], ws->ctl.p, cbytes, hipMemcpyDeviceToHost, s));
+    DI_HIP(hipEventRecord(ws->ev[slot], s));
+    obs[slot] = r;
+  };
+  const int fixed = check_every > 0 ? check_every : 0;
+  int next = fixed ? fixed : 8;
+  int cur = 0;
+  launch_chunk(next, cur);
   double nf_prev = -1.0;
   int r_prev = 0;
   for (;;) {
-    for (int i = 0; i < chunk; ++i) launch_round(a, sched, r++, 0, s, lt);
-    read_ctl(ws, a.nvec, s);
+    launch_chunk(next, 1 - cur);  // queued before looking at the previous chunk
+    DI_HIP(hipEventSynchronize(ws->ev[cur]));
+    const Ctl* h = hb[cur];
     double nf_max = 0.0;
     bool all = true;
     for (int v = 0; v < a.nvec; ++v) {
@@ -982,19 +1008,20 @@ static void run_rounds(const DiArgs<T>& a, Workspace* ws, int sched, int check_e
       }
     }
     if (all) break;
-    if (check_every == 0) {
-      // Predict the rounds left from the observed per-round decay of ||F||_1
-      // of the slowest vector.
-      int next = 8;
-      if (nf_prev > 0.0 && nf_max > 0.0 && nf_max < nf_prev && r > r_prev) {
-        const double q = std::pow(nf_max / nf_prev, 1.0 / (r - r_prev));
+    if (!fixed) {
+      // Rounds still needed after the observed one, predicted from the decay of
+      // ||F||_1 of the slowest vector, minus those already queued behind it.
+      int need = 8;
+      if (nf_prev > 0.0 && nf_max > 0.0 && nf_max < nf_prev && obs[cur] > r_prev) {
+        const double q = std::pow(nf_max / nf_prev, 1.0 / (obs[cur] - r_prev));
         if (q > 0.0 && q < 1.0)
-          next = (int)std::ceil(std::log(a.tol / nf_max) / std::log(q) * 1.15) + 2;
+          need = (int)std::ceil(std::log(a.tol / nf_max) / std::log(q) * 1.05) + 1;
       }
-      chunk = std::max(2, std::min(next, 64));
       nf_prev = nf_max;
-      r_prev = r;
+      r_prev = obs[cur];
+      next = std::max(2, std::min(need - (r - obs[cur]), 64));
     }
+    cur = 1 - cur;
   }
 }
 
