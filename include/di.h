@@ -142,6 +142,17 @@ typedef struct di_stats {
 di_status di_graph_create(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                           const double* w, void* stream, di_graph** out);
 di_status di_graph_destroy(di_graph* g); /* DI_EBUSY while a server references it */
+
+/*
+ * The binned scatter's layout that solves on a graph of n nodes get under
+ * the given knobs (tune may be NULL = defaults): windows of 2^window_log2
+ * nodes, with the per-window segment tables in LDS (*global_tables = 0) or
+ * read from global memory (1).  Host only: touches no device.  DI_EINVAL if
+ * no layout fits (n above 134,217,728 nodes, or tune->tables = 1 above
+ * ~25M nodes) or if an output pointer is NULL.
+ */
+di_status di_window_layout(int64_t n, const di_tune* tune, int32_t* window_log2,
+                           int32_t* global_tables);
 di_status di_graph_info(const di_graph* g, int64_t* n, int64_t* nnz, int64_t* n_dangling);
 
 /* --------------------------------------------------------- single solves */

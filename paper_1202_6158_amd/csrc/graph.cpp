@@ -32,7 +32,10 @@ size_t round_lds_bytes(int wlog, int nb, bool global_tables) {
 }
 
 int window_log2_for(int64_t n, int requested, int tables, bool* global_tables) {
-  constexpr size_t kLdsBudget = 136 * 1024;  // 160 KiB minus the round kernel's static LDS (22 KiB)
+  // 160 KiB per workgroup minus the round kernel's static LDS (21.5 KiB at 512
+  // threads, 21.6 KiB at 1024); the global-table layout always runs the
+  // 1024-thread instance, which leaves it a little more
+  constexpr size_t kLdsBudget = 136 * 1024, kLdsBudgetGlobal = 138 * 1024;
   int k0 = 8;
   if (requested >= 8) {
     k0 = std::min(requested, 14);
@@ -43,10 +46,11 @@ int window_log2_for(int64_t n, int requested, int tables, bool* global_tables) {
   for (const bool gt : {false, true}) {
     if ((gt && tables == 1) || (!gt && tables == 2)) continue;
     const int maxb = gt ? kMaxBucketsGlobal : kMaxBuckets;
+    const size_t budget = gt ? kLdsBudgetGlobal : kLdsBudget;
     int k = k0;
-    while (k > 8 && round_lds_bytes(k, nb_of(k), gt) > kLdsBudget) --k;
+    while (k > 8 && round_lds_bytes(k, nb_of(k), gt) > budget) --k;
     while (k < 14 && nb_of(k) > maxb) ++k;
-    if (nb_of(k) <= maxb && round_lds_bytes(k, nb_of(k), gt) <= kLdsBudget) {
+    if (nb_of(k) <= maxb && round_lds_bytes(k, nb_of(k), gt) <= budget) {
       if (global_tables) *global_tables = gt;
       return k;
     }
@@ -205,6 +209,21 @@ di_status di_graph_destroy(di_graph* g) {
       throw Fail{DI_EBUSY};
     }
     delete g;
+  });
+}
+
+di_status di_window_layout(int64_t n, const di_tune* tune, int32_t* window_log2,
+                           int32_t* global_tables) {
+  return guarded([&] {
+    DI_REQUIRE(window_log2 != nullptr && global_tables != nullptr, "NULL argument");
+    DI_REQUIRE(n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
+    const int tables = tune ? tune->tables : 0;
+    DI_REQUIRE(tables >= 0 && tables <= 2, "tables must be 0, 1 or 2");
+    bool gt = false;
+    const int k = window_log2_for(n, tune ? tune->window_log2 : 0, tables, &gt);
+    DI_REQUIRE(k > 0, "graph has too many nodes for the window tables");
+    *window_log2 = k;
+    *global_tables = gt ? 1 : 0;
   });
 }
 

@@ -112,6 +112,7 @@ _SIGS = {
     "di_graph_create": [ctypes.c_int64, ctypes.c_int64, _P, _P, _P, _P, _P],
     "di_graph_destroy": [_P],
     "di_graph_info": [_P, _P, _P, _P],
+    "di_window_layout": [ctypes.c_int64, ctypes.POINTER(Tune), _P, _P],
     "di_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_power_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_diffuse_round": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P],
@@ -147,6 +148,16 @@ def last_error() -> str:
 
 def version() -> str:
     return _lib.di_version().decode()
+
+
+def window_layout(n: int, tune=None):
+    """di_window_layout: (window_log2, global_tables) that solves on an
+    n-node graph get under the given knobs (host only)."""
+    k = ctypes.c_int32()
+    gt = ctypes.c_int32()
+    _check(_lib.di_window_layout(int(n), ctypes.byref(tune) if tune is not None else None,
+                                 ctypes.byref(k), ctypes.byref(gt)))
+    return k.value, bool(gt.value)
 
 
 def _check(rc: int, allow=()):

@@ -94,3 +94,26 @@ def test_autotune_rejects_missing_graph():
     rc = di._lib.di_autotune(None, di.TUNE_SOLVE, ctypes.byref(o), 0, None, None,
                              ctypes.byref(best), None, 0, None, None)
     assert rc == di.EINVAL and "graph" in di.last_error()
+
+
+@pytest.mark.parametrize("n,tune,expect", [
+    (10_000, None, (8, False)),            # about 512 windows, never below 2^8
+    (1_000_000, None, (11, False)),        # 489 windows of 2^11
+    (20_000_000, None, (13, False)),       # the LDS tables still fit at 2^13
+    (30_000_000, None, (13, True)),        # 3663 windows: tables in global memory
+    (134_217_728, None, (13, True)),       # the largest graph: 16384 windows
+    (10_000, dict(window_log2=14), (13, False)),  # 2^14 never fits the LDS budget
+    (10_000, dict(tables="global"), (8, True)),
+])
+def test_window_layout(n, tune, expect):
+    from paper_1202_6158_amd import di
+    t = di.make_tune("mean", 1.0, **tune) if tune else None
+    assert di.window_layout(n, t) == expect
+
+
+@pytest.mark.parametrize("n,tables", [(134_217_729, "auto"), (30_000_000, "lds"), (0, "auto")])
+def test_window_layout_rejects_what_does_not_fit(n, tables):
+    from paper_1202_6158_amd import di
+    with pytest.raises(di.DiError) as e:
+        di.window_layout(n, di.make_tune("mean", 1.0, tables=tables))
+    assert e.value.status == di.EINVAL
