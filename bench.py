@@ -135,20 +135,29 @@ def summarize_counters(fetch_csv, write_csv, knobs, copy_bytes=COPY_MIB << 20,
     import csv
 
     def per_kernel(path, counter):
-        vals, copy = [], []
+        rows, copy = [], []
         with open(path) as fh:
             for row in csv.DictReader(fh):
                 if row.get("Counter_Name") != counter:
                     continue
                 name, v = row.get("Kernel_Name", ""), float(row["Counter_Value"])
-                if "k_round" in name and v > 64.0:  # launches after the stop read ~nothing
-                    vals.append(v)
+                if "k_round" in name:
+                    rows.append((int(row.get("Dispatch_Id", 0) or 0), v))
                 elif "copyBuffer" in name:
                     copy.append(v)
-        return vals, copy
+        return [v for _, v in sorted(rows)], copy
 
-    f, fc = per_kernel(fetch_csv, "FETCH_SIZE")
-    w, wc = per_kernel(write_csv, "WRITE_SIZE")
+    fa, fc = per_kernel(fetch_csv, "FETCH_SIZE")
+    wa, wc = per_kernel(write_csv, "WRITE_SIZE")
+    # Launches issued after a solve stopped load their inputs, see the stop and
+    # return: they write nothing.  Both runs launch the same sequence, so the
+    # write run tells the working launches of both.
+    if len(fa) == len(wa):
+        keep = [w > 64.0 for w in wa]
+        f = [v for v, k in zip(fa, keep) if k]
+        w = [v for v, k in zip(wa, keep) if k]
+    else:
+        f, w = [v for v in fa if v > 64.0], [v for v in wa if v > 64.0]
     fkib, wkib = sum(f) / len(f), sum(w) / len(w)
     # the calibration copy reads and writes copy_bytes: its largest dispatch
     cf = max(fc) * 1024.0 / copy_bytes if fc else 1.0

@@ -51,10 +51,11 @@ def test_summarize_counters_scales_by_the_copy(bench, tmp_path):
     kr = "void di::k_round<float, 1, 512>(di::DiArgs<float>, int, int)"
     fetch = tmp_path / "fetch.csv"
     write = tmp_path / "write.csv"
-    # two working dispatches, one launch after the stop (ignored), the copy
-    _counter_csv(fetch, "FETCH_SIZE", [(kr, 1000.0), (kr, 3000.0), (kr, 10.0),
+    # two working dispatches and one launch after the stop, which loads its
+    # inputs (a large FETCH) but writes nothing: the write run excludes it from both
+    _counter_csv(fetch, "FETCH_SIZE", [(kr, 1000.0), (kr, 3000.0), (kr, 900.0),
                                        ("__amd_rocclr_copyBuffer", copy_kib * 0.5)])
-    _counter_csv(write, "WRITE_SIZE", [(kr, 500.0), (kr, 700.0), (kr, 2.0),
+    _counter_csv(write, "WRITE_SIZE", [(kr, 500.0), (kr, 700.0), (kr, 0.0),
                                        ("__amd_rocclr_copyBuffer", copy_kib * 1.0)])
     out = tmp_path / "traffic.json"
     knobs = ["op2", 0.03125, 11, 512]
