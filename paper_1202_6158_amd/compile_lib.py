@@ -47,8 +47,16 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
     os.replace(tmp, OUT)
+    # a C program that uses the ABI alone (examples/pagerank_edges.c)
+    ex_src = os.path.join(HERE, "examples", "pagerank_edges.c")
+    ex_out = os.path.join(HERE, "examples", "pagerank_edges")
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-I", os.path.join(ROOT, "include"), ex_src,
+           "-L", HERE, "-ldi", "-Wl,-rpath,$ORIGIN/..", "-o", ex_out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("example build failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", ex_out)
     return OUT
 
 
