@@ -151,6 +151,21 @@ def test_launch_shapes_limit_parity(di, c1, wlog, threads):
     assert _l1(x.cpu().numpy(), xs) <= st["err_bound_l1"] + 1e-6
 
 
+@pytest.mark.parametrize("check_every", [1, 3, 64])
+def test_fixed_check_intervals_reach_the_limit(di, c1, check_every):
+    """The host polls the control blocks every check_every rounds (the next
+    chunk already queued): the solve stops on the same round, whatever the
+    interval, and reaches the oracle's limit."""
+    g, Y, xs = c1
+    G = di.Graph(g)
+    tune = di.make_tune("op2", 0.5, check_every=check_every)
+    x, st = di.solve(G, d=D, tol=1e-12, precision="fp64", tune=tune)
+    _, ref = di.solve(G, d=D, tol=1e-12, precision="fp64", tune=di.make_tune("op2", 0.5))
+    assert abs(st["rounds"] - ref["rounds"]) <= 1
+    assert st["residual_l1"] < 1e-12
+    assert _l1(x.cpu().numpy(), xs) <= st["err_bound_l1"] + 1e-12
+
+
 def test_c1_fp32_limit_parity(di, c1):
     g, Y, xs = c1
     G = di.Graph(g)
