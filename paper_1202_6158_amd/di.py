@@ -172,8 +172,9 @@ def _torch():
 
 
 def _stream(stream):
+    """hipStream_t for a torch stream, a raw handle, or None (torch's current stream)."""
     if stream is not None:
-        return ctypes.c_void_p(int(stream))
+        return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
     torch = _torch()
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 

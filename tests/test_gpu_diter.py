@@ -313,3 +313,38 @@ def test_c2_fp32_theorem1_and_bound(di, c2):
     assert _l1(x.cpu().numpy(), xs) <= st["err_bound_l1"] + 1e-6
     xp, sp = di.power_solve(G, d=D, tol=1e-8, precision="fp64")
     assert _l1(xp.cpu().numpy(), xs) <= sp["err_bound_l1"] + 1e-12
+
+
+def test_concurrent_solves_on_one_graph(di, c1):
+    """Four host threads, each with its own stream, solve personalised vectors
+    on the same resident graph at once (each call takes its own workspace from
+    the graph's pool): every result equals the same solve run alone."""
+    import threading
+    import torch
+    g, _, _ = c1
+    G = di.Graph(g)
+    rng = np.random.default_rng(77)
+    vs = [wl.seed_vector(g.n, np.sort(rng.choice(g.n, 30, replace=False))) for _ in range(12)]
+    alone = [di.solve(G, v=v, d=D, tol=1e-12, precision="fp64")[0].cpu().numpy() for v in vs]
+    out = [None] * len(vs)
+    errors = []
+
+    def worker(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for i in range(k, len(vs), 4):
+                    x, _ = di.solve(G, v=vs[i], d=D, tol=1e-12, precision="fp64", stream=s)
+                    s.synchronize()
+                    out[i] = x.cpu().numpy()
+        except Exception as e:  # reported below, on the test's thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(120)
+    assert not errors, errors
+    for i in range(len(vs)):
+        assert out[i] is not None and _l1(out[i], alone[i]) <= 1e-13, i
