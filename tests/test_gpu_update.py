@@ -105,3 +105,27 @@ def test_inject_rejects_mismatched_graphs(di):
     with pytest.raises(di.DiError) as e:
         di.inject_update(a, b, F, H)
     assert e.value.status == di.EINVAL
+
+
+@pytest.mark.timeout(600)
+def test_update_at_one_million_nodes(di):
+    """The benchmark's update at full size: 1% of the 10^6-node graph's rows get
+    new out-links after an fp32 solve; inject + resume to 1e-8.  Theorem 1 for
+    P' on every node of the device state, and agreement with the power
+    iteration on P' within both bounds."""
+    import torch
+    g0 = wl.recipe("powerlaw-1m")
+    g1 = wl.modify_graph(g0, 0.01, seed=78)
+    G0, G1 = di.Graph(g0), di.Graph(g1)
+    F, H = _state(di, G0, g0, "fp32", 1e-8)
+    di.inject_update(G0, G1, F, H, d=D)
+    x, st = di.solve(G1, d=D, tol=1e-8, precision="fp32", state=(F, H))
+    assert st["residual_l1"] < 1e-8
+    Hn, Fn = H.cpu().numpy(), F.cpu().numpy().astype(np.float64)
+    deg = np.diff(g1.row_ptr)
+    src = np.repeat(np.arange(g1.n, dtype=np.int32), deg)
+    PH = np.bincount(g1.col_idx, weights=Hn[src] / deg[src], minlength=g1.n)
+    assert np.abs(Hn + Fn - ((1 - D) / g1.n + D * PH)).sum() < 1e-6
+    xp, sp = di.power_solve(G1, d=D, tol=1e-10, precision="fp64")
+    l1 = float(torch.sum(torch.abs(x - xp)).item())
+    assert l1 <= st["err_bound_l1"] + sp["err_bound_l1"] + 1e-6
