@@ -183,3 +183,34 @@ def test_server_launch_shapes(di, graphs, sched, c, wlog, threads):
         assert r["residual_l1"] < tol
         check_topk(r, oracle.limit(g, D, wl.seed_vector(g.n, seeds), tol=1e-14), 30, 1e-6)
     srv.close()
+
+
+@pytest.mark.timeout(600)
+def test_server_on_the_five_million_node_serving_graph(di):
+    """Served requests on the largest serving graph (5*10^6 nodes, 5*10^7
+    links) at the stream's tolerances: each top-k within the reported bound
+    (plus the comparator's own) of the GPU power iteration run on the same
+    personalisation vector, an independent kernel on the in-link CSR."""
+    import torch
+    g = wl.recipe("serve-5m")
+    G = di.Graph(g)
+    srv = di.Server(hbm_budget_bytes=16 << 30, max_slots=8, topk=50)
+    gid = srv.add_graph(G)
+    rng = np.random.default_rng(91)
+    reqs = []
+    for q, tol in enumerate([1e-4, 1e-6, 1e-8, 1e-6]):
+        s = int(np.exp(rng.uniform(0, np.log(1000))))
+        seeds = np.sort(rng.choice(g.n, size=max(s, 1), replace=False)).astype(np.int32)
+        reqs.append((seeds, tol, srv.submit(gid, seeds, d=D, tol=tol)))
+    for seeds, tol, rid in reqs:
+        r = srv.wait(rid, 300.0)
+        assert r is not None and r["status"] == 0 and r["residual_l1"] < tol
+        v = torch.from_numpy(wl.seed_vector(g.n, seeds)).cuda()
+        xp, sp = di.power_solve(G, v=v, d=D, tol=1e-10, precision="fp64")
+        xp = xp.cpu().numpy()
+        ids, vals = r["top_ids"], r["top_x"]
+        slack = r["err_bound_l1"] + sp["err_bound_l1"] + 1e-9
+        assert np.all(np.diff(vals) <= 0)
+        assert np.all(np.abs(vals - xp[ids]) <= slack)
+        assert np.sort(xp)[::-1][len(ids) - 1] <= vals[-1] + 2 * slack
+    srv.close()
