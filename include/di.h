@@ -223,6 +223,20 @@ di_status di_solve_batch(const di_graph* g, int32_t B, const int64_t* seed_ptr,
                          const int32_t* seeds, const double* seed_w, const di_opts* opts,
                          double* x, di_stats* stats, void* stream);
 
+/*
+ * di_solve_batch keeping only each vector's topk largest entries (the B x n
+ * result is never formed outside the device): top_ids int32[B*topk] holds
+ * the node ids, largest value first, ties by id, and -1 past the vector's
+ * last non-zero entry; top_x double[B*topk] the values (normalised as
+ * opts->normalize says; 0 past the last non-zero entry).  Both host arrays,
+ * row-major by vector.  Same seed sets, options and errors as
+ * di_solve_batch; DI_EINVAL unless 1 <= topk <= 1024.
+ */
+di_status di_solve_batch_topk(const di_graph* g, int32_t B, const int64_t* seed_ptr,
+                              const int32_t* seeds, const double* seed_w, const di_opts* opts,
+                              int32_t topk, int32_t* top_ids, double* top_x, di_stats* stats,
+                              void* stream);
+
 /* -------------------------------------------------------------- autotuner */
 
 #define DI_TUNE_SOLVE 0 /* tune single solves (uniform V) */

@@ -1166,116 +1166,6 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   return status_of(*h);
 }
 
-template <typename T>
-static di_status batch_impl(Graph* g, int32_t B, const int64_t* seed_ptr, const int32_t* seeds,
-                            const double* seed_w, const di_opts* o, double* x, di_stats* st,
-                            hipStream_t s) {
-  const TuneParams tp = tune_params(g, o->tune, DI_TUNE_BATCH, o->precision);
-  const bool dev = (o->flags & DI_DEVICE_PTRS) != 0;
-  const int64_t n = g->n;
-  const int64_t max_rounds = o->max_rounds > 0 ? o->max_rounds : 1000000;
-  // Validation of the seed sets (host arrays).
-  DI_REQUIRE(B >= 1, "B must be >= 1");
-  DI_REQUIRE(seed_ptr && seeds, "seed_ptr and seeds are required");
-  DI_REQUIRE(seed_ptr[0] == 0, "seed_ptr[0] must be 0");
-  {
-    std::vector<int32_t> tmp;
-    for (int32_t b = 0; b < B; ++b) {
-      DI_REQUIRE(seed_ptr[b + 1] > seed_ptr[b], "empty seed set");
-      tmp.assign(seeds + seed_ptr[b], seeds + seed_ptr[b + 1]);
-      double ws = 0.0;
-      for (int64_t k = seed_ptr[b]; k < seed_ptr[b + 1]; ++k) {
-        DI_REQUIRE(seeds[k] >= 0 && seeds[k] < n, "seed out of range");
-        if (seed_w) {
-          DI_REQUIRE(std::isfinite(seed_w[k]) && seed_w[k] >= 0.0,
-                     "seed weight negative or not finite");
-          ws += seed_w[k];
-        }
-      }
-      if (seed_w) DI_REQUIRE(std::fabs(ws - 1.0) <= 1e-9, "seed weights of a set must sum to 1");
-      std::sort(tmp.begin(), tmp.end());
-      DI_REQUIRE(std::adjacent_find(tmp.begin(), tmp.end()) == tmp.end(), "repeated seed in a set");
-    }
-  }
-  // Vectors per group: what 80% of the free device memory holds.
-  size_t free_b = 0, total_b = 0;
-  DI_HIP(hipMemGetInfo(&free_b, &total_b));
-  const int nb = (int)((n + (1ll << tp.wlog) - 1) >> tp.wlog);
-  const int64_t per = bytes_per_vector(n, g->m, nb, o->precision);
-  int group = (int)std::max<int64_t>(1, std::min<int64_t>(B, (int64_t)(0.8 * (double)free_b) / per));
-  WsGuard guard{g, acquire_batch_workspace(g, o->precision, tp.wlog, tp.gt, std::max(group, 2)),
-                s};
-  Workspace* ws = guard.ws;
-  group = std::min(group, ws->nvec);
-  DevBuf d_ptr, d_seeds, d_w, d_x;
-  const int64_t nseeds = seed_ptr[B];
-  d_ptr.alloc((B + 1) * 8);
-  d_seeds.alloc(nseeds * 4);
-  if (seed_w) d_w.alloc(nseeds * 8);
-  if (x && !dev) d_x.alloc((int64_t)group * n * 8);
-  di_status worst = DI_OK;
-  for (int32_t b0 = 0; b0 < B; b0 += group) {
-    const int gb = std::min<int32_t>(group, B - b0);
-    // seed pointers of this group, rebased to 0
-    std::vector<int64_t> ptr(gb + 1);
-    for (int k = 0; k <= gb; ++k) ptr[k] = seed_ptr[b0 + k] - seed_ptr[b0];
-    DI_HIP(hipMemcpyAsync(d_ptr.p, ptr.data(), (gb + 1) * 8, hipMemcpyHostToDevice, s));
-    DI_HIP(hipMemcpyAsync(d_seeds.p, seeds + seed_ptr[b0], ptr[gb] * 4, hipMemcpyHostToDevice, s));
-    if (seed_w)
-      DI_HIP(hipMemcpyAsync(d_w.p, seed_w + seed_ptr[b0], ptr[gb] * 8, hipMemcpyHostToDevice, s));
-    DiArgs<T> a = make_args<T>(g, ws, o->d, o->tol, tp.c, max_rounds, ws->F.as<T>(),
-                               ws->H.as<double>(), gb);
-    a.threads = tp.threads;
-    EventTimer timer(s);
-    k_init<T><<<dim3(grid_for(n, 256), gb), kBlock, 0, s>>>(a, nullptr, 0, 1);
-    DI_HIP(hipGetLastError());
-    k_seed<T><<<gb, 256, 0, s>>>(a, d_ptr.as<int64_t>(), d_seeds.as<int32_t>(),
-                                  seed_w ? d_w.as<double>() : nullptr);
-    DI_HIP(hipGetLastError());
-    run_rounds(a, ws, tp.sched, tp.check_every, s, nullptr);
-    double* xo = x ? (dev ? x + (int64_t)b0 * n : d_x.as<double>()) : nullptr;
-    flush(a, xo, o->normalize, s);
-    const double secs = timer.stop();
-    if (x && !dev)
-      DI_HIP(hipMemcpyAsync(x + (int64_t)b0 * n, xo, (int64_t)gb * n * 8, hipMemcpyDeviceToHost, s));
-    read_ctl(ws, gb, s);
-    const Ctl* h = ws->hctl.as<Ctl>();
-    for (int k = 0; k < gb; ++k) {
-      if (st) fill_stats(h[k], o, secs, &st[b0 + k]);
-      const di_status rc = status_of(h[k]);
-      if (rc == DI_EDEVICE || (rc == DI_ENOTCONV && worst == DI_OK)) worst = rc;
-    }
-  }
-  return worst;
-}
-
-template <typename T>
-static void round_impl(Graph* g, double d, double theta, T* F, double* H, int64_t* tn,
-                       int64_t* te, hipStream_t s) {
-  bool gt = false;
-  const int wlog = window_log2_for(g->n, 0, 0, &gt);
-  DI_REQUIRE(wlog > 0, "graph has too many nodes for the window tables");
-  WsGuard guard{g,
-                acquire_workspace(g, std::is_same<T, double>::value ? DI_FP64 : DI_FP32_FLUID, wlog,
-                                  gt),
-                s};
-  Workspace* ws = guard.ws;
-  DiArgs<T> a = make_args<T>(g, ws, d, 0.0, 1.0, (int64_t)1 << 40, F, H, 1);
-  a.theta0 = theta;
-  k_init<T><<<dim3(grid_for(g->n, 2048), 1), kBlock, 0, s>>>(a, nullptr, 1, 0);
-  DI_HIP(hipGetLastError());
-  launch_round(a, DI_SCHED_MEAN, 0, 0, s);
-  launch_round(a, DI_SCHED_MEAN, 1, 1, s);
-  read_ctl(ws, 1, s);
-  const Ctl* h = ws->hctl.as<Ctl>();
-  if (h->err) {
-    set_error("internal segment consistency check failed");
-    throw Fail{DI_EDEVICE};
-  }
-  if (tn) *tn = h->last_taken;
-  if (te) *te = h->last_edges;
-}
-
 // ------------------------------------------------------------------ top-k
 
 constexpr int kTopBins = 2048;  // key prefix histogram (non-negative float bits >> shift)
@@ -1339,6 +1229,249 @@ __global__ __launch_bounds__(kBlock) void k_topk_collect(DiArgs<T> a, const uint
   }
 }
 
+// The kk largest entries of H+F of k vectors (a.vmap[0..k)) on the device:
+// a histogram of the fp32 key's top bits picks a threshold that at least kk
+// entries reach (refined by the next 11 bits when too many share its bin),
+// the entries above it are collected, and the host sorts that short list.
+template <typename T>
+class TopKT {
+ public:
+  static constexpr int kCap = 8192;  // candidates kept per vector
+
+  void reserve(int cap) {
+    hist_.alloc((int64_t)cap * kTopBins * 4);
+    h_hist_.alloc((int64_t)cap * kTopBins * 4);
+    par_.alloc(cap * 4);
+    h_par_.alloc(cap * 4);
+    thr_.alloc(cap * 4);
+    h_thr_.alloc(cap * 4);
+    ccount_.alloc(cap * 4);
+    h_ccount_.alloc(cap * 4);
+    cval_.alloc((int64_t)cap * kCap * 8);
+    cid_.alloc((int64_t)cap * kCap * 4);
+    h_cval_.alloc((int64_t)cap * kCap * 8);
+    h_cid_.alloc((int64_t)cap * kCap * 4);
+  }
+
+  // out[q]: up to kk (value of H+F, node) pairs of vector a.vmap[q], largest
+  // first, ties by node id; fewer when fewer entries are non-zero.
+  void run(const DiArgs<T>& a, int k, int kk,
+           std::vector<std::vector<std::pair<double, int32_t>>>& out, hipStream_t s) {
+    const int gx = grid_for(a.n, 512);
+    DI_HIP(hipMemsetAsync(hist_.p, 0, (int64_t)k * kTopBins * 4, s));
+    k_topk_hist<T><<<dim3(gx, k), kBlock, 0, s>>>(a, 20, nullptr, hist_.as<int32_t>());
+    DI_HIP(hipGetLastError());
+    DI_HIP(hipMemcpyAsync(h_hist_.p, hist_.p, (int64_t)k * kTopBins * 4, hipMemcpyDeviceToHost, s));
+    DI_HIP(hipStreamSynchronize(s));
+    const int32_t* hh = h_hist_.as<int32_t>();
+    int32_t* par = h_par_.as<int32_t>();
+    uint32_t* thr = h_thr_.as<uint32_t>();
+    bool refine = false;
+    std::vector<int64_t> above(k, 0);
+    for (int q = 0; q < k; ++q) {
+      const int32_t* h = hh + (int64_t)q * kTopBins;
+      int64_t cum = 0;
+      int b = kTopBins - 1;
+      for (; b > 0; --b) {
+        if (cum + h[b] >= kk) break;
+        cum += h[b];
+      }
+      // fewer than kk non-zero entries: take every non-zero one (bins >= 1)
+      par[q] = b >= 1 && cum + h[b] > kCap ? b : -1;
+      above[q] = cum;
+      thr[q] = (uint32_t)std::max(b, 1) << 11;  // key >> 9 >= b << 11  <=>  key >> 20 >= b
+      if (par[q] >= 0) refine = true;
+    }
+    if (refine) {
+      DI_HIP(hipMemcpyAsync(par_.p, h_par_.p, k * 4, hipMemcpyHostToDevice, s));
+      DI_HIP(hipMemsetAsync(hist_.p, 0, (int64_t)k * kTopBins * 4, s));
+      k_topk_hist<T><<<dim3(gx, k), kBlock, 0, s>>>(a, 9, par_.as<int32_t>(), hist_.as<int32_t>());
+      DI_HIP(hipGetLastError());
+      DI_HIP(hipMemcpyAsync(h_hist_.p, hist_.p, (int64_t)k * kTopBins * 4, hipMemcpyDeviceToHost,
+                            s));
+      DI_HIP(hipStreamSynchronize(s));
+      for (int q = 0; q < k; ++q) {
+        if (par[q] < 0) continue;
+        const int32_t* h = hh + (int64_t)q * kTopBins;
+        int64_t cum = above[q];
+        int b = kTopBins - 1;
+        for (; b > 0; --b) {
+          if (cum + h[b] >= kk) break;
+          cum += h[b];
+        }
+        thr[q] = ((uint32_t)par[q] << 11) | (uint32_t)b;
+      }
+    }
+    DI_HIP(hipMemcpyAsync(thr_.p, h_thr_.p, k * 4, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemsetAsync(ccount_.p, 0, k * 4, s));
+    k_topk_collect<T><<<dim3(gx, k), kBlock, 0, s>>>(a, thr_.as<uint32_t>(), cval_.as<double>(),
+                                                      cid_.as<int32_t>(), ccount_.as<int32_t>(),
+                                                      kCap);
+    DI_HIP(hipGetLastError());
+    DI_HIP(hipMemcpyAsync(h_ccount_.p, ccount_.p, k * 4, hipMemcpyDeviceToHost, s));
+    DI_HIP(hipMemcpyAsync(h_cval_.p, cval_.p, (int64_t)k * kCap * 8, hipMemcpyDeviceToHost, s));
+    DI_HIP(hipMemcpyAsync(h_cid_.p, cid_.p, (int64_t)k * kCap * 4, hipMemcpyDeviceToHost, s));
+    DI_HIP(hipStreamSynchronize(s));
+    const int32_t* cc = h_ccount_.as<int32_t>();
+    out.assign(k, {});
+    for (int q = 0; q < k; ++q) {
+      const int nc = std::min(cc[q], kCap);
+      std::vector<std::pair<double, int32_t>>& v = out[q];
+      v.resize(nc);
+      for (int t = 0; t < nc; ++t)
+        v[t] = {h_cval_.as<double>()[(int64_t)q * kCap + t], h_cid_.as<int32_t>()[(int64_t)q * kCap + t]};
+      std::sort(v.begin(), v.end(), [](const auto& x, const auto& y) {
+        return x.first > y.first || (x.first == y.first && x.second < y.second);
+      });
+      if ((int)v.size() > kk) v.resize(kk);
+    }
+  }
+
+ private:
+  DevBuf hist_, par_, thr_, ccount_, cval_, cid_;
+  PinnedBuf h_hist_, h_par_, h_thr_, h_ccount_, h_cval_, h_cid_;
+};
+
+template <typename T>
+static di_status batch_impl(Graph* g, int32_t B, const int64_t* seed_ptr, const int32_t* seeds,
+                            const double* seed_w, const di_opts* o, double* x, di_stats* st,
+                            hipStream_t s, int32_t topk = 0, int32_t* top_ids = nullptr,
+                            double* top_x = nullptr) {
+  const TuneParams tp = tune_params(g, o->tune, DI_TUNE_BATCH, o->precision);
+  const bool dev = (o->flags & DI_DEVICE_PTRS) != 0;
+  const int64_t n = g->n;
+  const int64_t max_rounds = o->max_rounds > 0 ? o->max_rounds : 1000000;
+  // Validation of the seed sets (host arrays).
+  DI_REQUIRE(B >= 1, "B must be >= 1");
+  DI_REQUIRE(seed_ptr && seeds, "seed_ptr and seeds are required");
+  DI_REQUIRE(seed_ptr[0] == 0, "seed_ptr[0] must be 0");
+  {
+    std::vector<int32_t> tmp;
+    for (int32_t b = 0; b < B; ++b) {
+      DI_REQUIRE(seed_ptr[b + 1] > seed_ptr[b], "empty seed set");
+      tmp.assign(seeds + seed_ptr[b], seeds + seed_ptr[b + 1]);
+      double ws = 0.0;
+      for (int64_t k = seed_ptr[b]; k < seed_ptr[b + 1]; ++k) {
+        DI_REQUIRE(seeds[k] >= 0 && seeds[k] < n, "seed out of range");
+        if (seed_w) {
+          DI_REQUIRE(std::isfinite(seed_w[k]) && seed_w[k] >= 0.0,
+                     "seed weight negative or not finite");
+          ws += seed_w[k];
+        }
+      }
+      if (seed_w) DI_REQUIRE(std::fabs(ws - 1.0) <= 1e-9, "seed weights of a set must sum to 1");
+      std::sort(tmp.begin(), tmp.end());
+      DI_REQUIRE(std::adjacent_find(tmp.begin(), tmp.end()) == tmp.end(), "repeated seed in a set");
+    }
+  }
+  // Vectors per group: what 80% of the free device memory holds.
+  size_t free_b = 0, total_b = 0;
+  DI_HIP(hipMemGetInfo(&free_b, &total_b));
+  const int nb = (int)((n + (1ll << tp.wlog) - 1) >> tp.wlog);
+  const int64_t per = bytes_per_vector(n, g->m, nb, o->precision);
+  int group = (int)std::max<int64_t>(1, std::min<int64_t>(B, (int64_t)(0.8 * (double)free_b) / per));
+  WsGuard guard{g, acquire_batch_workspace(g, o->precision, tp.wlog, tp.gt, std::max(group, 2)),
+                s};
+  Workspace* ws = guard.ws;
+  group = std::min(group, ws->nvec);
+  DevBuf d_ptr, d_seeds, d_w, d_x;
+  const int64_t nseeds = seed_ptr[B];
+  d_ptr.alloc((B + 1) * 8);
+  d_seeds.alloc(nseeds * 4);
+  if (seed_w) d_w.alloc(nseeds * 8);
+  if (x && !dev) d_x.alloc((int64_t)group * n * 8);
+  // top-k outputs: the vectors of a group by identity slot map
+  TopKT<T> tk;
+  DevBuf ident;
+  if (topk > 0) {
+    tk.reserve(group);
+    std::vector<int32_t> id(group);
+    for (int k = 0; k < group; ++k) id[k] = k;
+    ident.alloc(group * 4);
+    DI_HIP(hipMemcpyAsync(ident.p, id.data(), group * 4, hipMemcpyHostToDevice, s));
+    DI_HIP(hipStreamSynchronize(s));
+  }
+  di_status worst = DI_OK;
+  for (int32_t b0 = 0; b0 < B; b0 += group) {
+    const int gb = std::min<int32_t>(group, B - b0);
+    // seed pointers of this group, rebased to 0
+    std::vector<int64_t> ptr(gb + 1);
+    for (int k = 0; k <= gb; ++k) ptr[k] = seed_ptr[b0 + k] - seed_ptr[b0];
+    DI_HIP(hipMemcpyAsync(d_ptr.p, ptr.data(), (gb + 1) * 8, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemcpyAsync(d_seeds.p, seeds + seed_ptr[b0], ptr[gb] * 4, hipMemcpyHostToDevice, s));
+    if (seed_w)
+      DI_HIP(hipMemcpyAsync(d_w.p, seed_w + seed_ptr[b0], ptr[gb] * 8, hipMemcpyHostToDevice, s));
+    DiArgs<T> a = make_args<T>(g, ws, o->d, o->tol, tp.c, max_rounds, ws->F.as<T>(),
+                               ws->H.as<double>(), gb);
+    a.threads = tp.threads;
+    EventTimer timer(s);
+    k_init<T><<<dim3(grid_for(n, 256), gb), kBlock, 0, s>>>(a, nullptr, 0, 1);
+    DI_HIP(hipGetLastError());
+    k_seed<T><<<gb, 256, 0, s>>>(a, d_ptr.as<int64_t>(), d_seeds.as<int32_t>(),
+                                  seed_w ? d_w.as<double>() : nullptr);
+    DI_HIP(hipGetLastError());
+    run_rounds(a, ws, tp.sched, tp.check_every, s, nullptr);
+    double* xo = x ? (dev ? x + (int64_t)b0 * n : d_x.as<double>()) : nullptr;
+    flush(a, xo, o->normalize, s);
+    const double secs = timer.stop();
+    if (x && !dev)
+      DI_HIP(hipMemcpyAsync(x + (int64_t)b0 * n, xo, (int64_t)gb * n * 8, hipMemcpyDeviceToHost, s));
+    read_ctl(ws, gb, s);
+    const Ctl* h = ws->hctl.as<Ctl>();
+    if (topk > 0) {
+      DiArgs<T> at = a;
+      at.vmap = ident.as<int32_t>();
+      std::vector<std::vector<std::pair<double, int32_t>>> cand;
+      tk.run(at, gb, (int)std::min<int64_t>(topk, n), cand, s);
+      for (int k = 0; k < gb; ++k) {
+        const double S = h[k].fl[0];
+        const double scale = o->normalize && S > 0 ? 1.0 / S : 1.0;
+        int32_t* ids = top_ids + (int64_t)(b0 + k) * topk;
+        double* xs = top_x + (int64_t)(b0 + k) * topk;
+        for (int t = 0; t < topk; ++t) {
+          const bool has = t < (int)cand[k].size();
+          ids[t] = has ? cand[k][t].second : -1;
+          xs[t] = has ? cand[k][t].first * scale : 0.0;
+        }
+      }
+    }
+    for (int k = 0; k < gb; ++k) {
+      if (st) fill_stats(h[k], o, secs, &st[b0 + k]);
+      const di_status rc = status_of(h[k]);
+      if (rc == DI_EDEVICE || (rc == DI_ENOTCONV && worst == DI_OK)) worst = rc;
+    }
+  }
+  return worst;
+}
+
+template <typename T>
+static void round_impl(Graph* g, double d, double theta, T* F, double* H, int64_t* tn,
+                       int64_t* te, hipStream_t s) {
+  bool gt = false;
+  const int wlog = window_log2_for(g->n, 0, 0, &gt);
+  DI_REQUIRE(wlog > 0, "graph has too many nodes for the window tables");
+  WsGuard guard{g,
+                acquire_workspace(g, std::is_same<T, double>::value ? DI_FP64 : DI_FP32_FLUID, wlog,
+                                  gt),
+                s};
+  Workspace* ws = guard.ws;
+  DiArgs<T> a = make_args<T>(g, ws, d, 0.0, 1.0, (int64_t)1 << 40, F, H, 1);
+  a.theta0 = theta;
+  k_init<T><<<dim3(grid_for(g->n, 2048), 1), kBlock, 0, s>>>(a, nullptr, 1, 0);
+  DI_HIP(hipGetLastError());
+  launch_round(a, DI_SCHED_MEAN, 0, 0, s);
+  launch_round(a, DI_SCHED_MEAN, 1, 1, s);
+  read_ctl(ws, 1, s);
+  const Ctl* h = ws->hctl.as<Ctl>();
+  if (h->err) {
+    set_error("internal segment consistency check failed");
+    throw Fail{DI_EDEVICE};
+  }
+  if (tn) *tn = h->last_taken;
+  if (te) *te = h->last_edges;
+}
+
+
 // ---------------------------------------------------------- serving engine
 
 int64_t slot_bytes(const Graph* g, int precision) {
@@ -1365,18 +1498,7 @@ class SlotPoolT : public SlotPool {
     h_vround_.alloc(capacity * 4);
     h_vd_.alloc(capacity * 8);
     h_vtol_.alloc(capacity * 8);
-    hist_.alloc((int64_t)capacity * kTopBins * 4);
-    h_hist_.alloc((int64_t)capacity * kTopBins * 4);
-    par_.alloc(capacity * 4);
-    h_par_.alloc(capacity * 4);
-    thr_.alloc(capacity * 4);
-    h_thr_.alloc(capacity * 4);
-    ccount_.alloc(capacity * 4);
-    h_ccount_.alloc(capacity * 4);
-    cval_.alloc((int64_t)capacity * kCap * 8);
-    cid_.alloc((int64_t)capacity * kCap * 4);
-    h_cval_.alloc((int64_t)capacity * kCap * 8);
-    h_cid_.alloc((int64_t)capacity * kCap * 4);
+    topk_.reserve(capacity);
   }
   ~SlotPoolT() override { delete ws_; }
   int capacity() const override { return cap_; }
@@ -1468,82 +1590,21 @@ class SlotPoolT : public SlotPool {
     DI_HIP(hipMemcpyAsync(vmap_.p, h_vmap_.p, k * 4, hipMemcpyHostToDevice, s));
     DiArgs<T> a = args(k);
     flush(a, nullptr, 1, s);
-    // key-prefix histogram (bits 30..20), then, where needed, the next 11 bits
-    const int gx = grid_for(g_->n, 512);
-    k_zero32(hist_.as<int32_t>(), (int64_t)k * kTopBins, s);
-    k_topk_hist<T><<<dim3(gx, k), kBlock, 0, s>>>(a, 20, nullptr, hist_.as<int32_t>());
-    DI_HIP(hipGetLastError());
-    DI_HIP(hipMemcpyAsync(h_hist_.p, hist_.p, (int64_t)k * kTopBins * 4, hipMemcpyDeviceToHost, s));
-    read_ctl(ws_, cap_, s);
-    const int32_t* hh = h_hist_.as<int32_t>();
-    int32_t* par = h_par_.as<int32_t>();
-    uint32_t* thr = h_thr_.as<uint32_t>();
     const int kk = (int)std::min<int64_t>(topk, g_->n);
-    bool refine = false;
-    std::vector<int64_t> above(k, 0);
-    for (int q = 0; q < k; ++q) {
-      const int32_t* h = hh + (int64_t)q * kTopBins;
-      int64_t cum = 0;
-      int b = kTopBins - 1;
-      for (; b > 0; --b) {
-        if (cum + h[b] >= kk) break;
-        cum += h[b];
-      }
-      // fewer than kk non-zero entries: take every non-zero one (bins >= 1)
-      par[q] = b >= 1 && cum + h[b] > kCap ? b : -1;
-      above[q] = cum;
-      thr[q] = (uint32_t)std::max(b, 1) << 11;  // key >> 9 >= b << 11  <=>  key >> 20 >= b
-      if (par[q] >= 0) refine = true;
-    }
-    if (refine) {
-      DI_HIP(hipMemcpyAsync(par_.p, h_par_.p, k * 4, hipMemcpyHostToDevice, s));
-      k_zero32(hist_.as<int32_t>(), (int64_t)k * kTopBins, s);
-      k_topk_hist<T><<<dim3(gx, k), kBlock, 0, s>>>(a, 9, par_.as<int32_t>(), hist_.as<int32_t>());
-      DI_HIP(hipGetLastError());
-      DI_HIP(hipMemcpyAsync(h_hist_.p, hist_.p, (int64_t)k * kTopBins * 4, hipMemcpyDeviceToHost,
-                            s));
-      DI_HIP(hipStreamSynchronize(s));
-      for (int q = 0; q < k; ++q) {
-        if (par[q] < 0) continue;
-        const int32_t* h = hh + (int64_t)q * kTopBins;
-        int64_t cum = above[q];
-        int b = kTopBins - 1;
-        for (; b > 0; --b) {
-          if (cum + h[b] >= kk) break;
-          cum += h[b];
-        }
-        thr[q] = ((uint32_t)par[q] << 11) | (uint32_t)b;
-      }
-    }
-    DI_HIP(hipMemcpyAsync(thr_.p, h_thr_.p, k * 4, hipMemcpyHostToDevice, s));
-    k_zero32(ccount_.as<int32_t>(), k, s);
-    k_topk_collect<T><<<dim3(gx, k), kBlock, 0, s>>>(a, thr_.as<uint32_t>(), cval_.as<double>(),
-                                                      cid_.as<int32_t>(), ccount_.as<int32_t>(),
-                                                      kCap);
-    DI_HIP(hipGetLastError());
-    DI_HIP(hipMemcpyAsync(h_ccount_.p, ccount_.p, k * 4, hipMemcpyDeviceToHost, s));
-    DI_HIP(hipMemcpyAsync(h_cval_.p, cval_.p, (int64_t)k * kCap * 8, hipMemcpyDeviceToHost, s));
-    DI_HIP(hipMemcpyAsync(h_cid_.p, cid_.p, (int64_t)k * kCap * 4, hipMemcpyDeviceToHost, s));
+    std::vector<std::vector<std::pair<double, int32_t>>> cand;
+    topk_.run(a, k, kk, cand, s);
     read_ctl(ws_, cap_, s);
     const Ctl* hc = ws_->hctl.as<Ctl>();
-    const int32_t* cc = h_ccount_.as<int32_t>();
     for (int q = 0; q < k; ++q) {
       const int slot = slots[q];
       const Ctl& c = hc[slot];
       SlotResult r;
       r.slot = slot;
       r.status = status_of(c);
-      const int nc = std::min(cc[q], kCap);
-      std::vector<std::pair<double, int32_t>> v(nc);
-      for (int t = 0; t < nc; ++t)
-        v[t] = {h_cval_.as<double>()[(int64_t)q * kCap + t], h_cid_.as<int32_t>()[(int64_t)q * kCap + t]};
-      std::sort(v.begin(), v.end(), [](const auto& x, const auto& y) {
-        return x.first > y.first || (x.first == y.first && x.second < y.second);
-      });
       const double S = c.fl[0];
-      for (int t = 0; t < nc && t < kk; ++t) {
-        r.ids.push_back(v[t].second);
-        r.x.push_back(S > 0 ? v[t].first / S : 0.0);
+      for (const auto& e : cand[q]) {
+        r.ids.push_back(e.second);
+        r.x.push_back(S > 0 ? e.first / S : 0.0);
       }
       const double d = d_[slot], nf = c.fl[2];
       r.residual = nf;
@@ -1555,7 +1616,6 @@ class SlotPoolT : public SlotPool {
   }
 
  private:
-  static constexpr int kCap = 8192;  // candidates kept per slot
   DiArgs<T> args(int k) {
     DiArgs<T> a = make_args<T>(g_, ws_, 0.85, 1e-6, tp_.c, 1000000, ws_->F.as<T>(),
                                ws_->H.as<double>(), k);
@@ -1565,18 +1625,15 @@ class SlotPoolT : public SlotPool {
     a.vtol = vtol_.as<double>();
     return a;
   }
-  static void k_zero32(int32_t* p, int64_t n, hipStream_t s) {
-    DI_HIP(hipMemsetAsync(p, 0, n * 4, s));
-  }
   Graph* g_;
   int cap_;
   TuneParams tp_;
   Workspace* ws_;
   std::vector<int> round_;
   std::vector<double> d_, tol_;
-  DevBuf vmap_, vround_, vd_, vtol_, hist_, par_, thr_, ccount_, cval_, cid_, sptr_, sseeds_, sw_;
-  PinnedBuf h_vmap_, h_vround_, h_vd_, h_vtol_, h_hist_, h_par_, h_thr_, h_ccount_, h_cval_, h_cid_,
-      h_sptr_, h_sseeds_, h_sw_;
+  TopKT<T> topk_;
+  DevBuf vmap_, vround_, vd_, vtol_, sptr_, sseeds_, sw_;
+  PinnedBuf h_vmap_, h_vround_, h_vd_, h_vtol_, h_sptr_, h_sseeds_, h_sw_;
 };
 
 SlotPool* make_slot_pool(Graph* g, int precision, int capacity, const di_tune* tune) {
@@ -1600,6 +1657,28 @@ di_status di_solve(const di_graph* gc, const double* v, const di_opts* opts, dou
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = opts->precision == DI_FP64 ? solve_impl<double>(g, v, opts, x, stats, s)
                                     : solve_impl<float>(g, v, opts, x, stats, s);
+  });
+  return g != DI_OK ? g : rc;
+}
+
+di_status di_solve_batch_topk(const di_graph* gc, int32_t B, const int64_t* seed_ptr,
+                              const int32_t* seeds, const double* seed_w, const di_opts* opts,
+                              int32_t topk, int32_t* top_ids, double* top_x, di_stats* stats,
+                              void* stream) {
+  di_status rc = DI_OK;
+  di_status g = guarded([&] {
+    DI_REQUIRE(gc != nullptr, "graph is NULL");
+    validate_d_tol(opts);
+    DI_REQUIRE((opts->flags & DI_RESUME) == 0, "DI_RESUME is not supported for batches");
+    DI_REQUIRE(topk >= 1 && topk <= 1024, "topk must be in [1, 1024]");
+    DI_REQUIRE(top_ids != nullptr && top_x != nullptr, "top_ids and top_x are required");
+    Graph* g = const_cast<di_graph*>(gc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = opts->precision == DI_FP64
+             ? batch_impl<double>(g, B, seed_ptr, seeds, seed_w, opts, nullptr, stats, s, topk,
+                                  top_ids, top_x)
+             : batch_impl<float>(g, B, seed_ptr, seeds, seed_w, opts, nullptr, stats, s, topk,
+                                 top_ids, top_x);
   });
   return g != DI_OK ? g : rc;
 }

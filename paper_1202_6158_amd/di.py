@@ -117,6 +117,8 @@ _SIGS = {
     "di_power_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_diffuse_round": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P],
     "di_solve_batch": [_P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _P],
+    "di_solve_batch_topk": [_P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(Opts), ctypes.c_int32,
+                            _P, _P, _P, _P],
     "di_inject_update": [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P, _P],
     "di_autotune": [_P, ctypes.c_int32, ctypes.POINTER(Opts), ctypes.c_int32, _P, _P,
                     ctypes.POINTER(Tune), _P, ctypes.c_int32, _P, _P],
@@ -360,6 +362,27 @@ def solve_batch(graph: Graph, seed_ptr, seeds, seed_w=None, d=0.85, tol=1e-6, pr
                              ctypes.byref(o), _ptr(x), st, _stream(stream))
     _check(rc, allow=(ENOTCONV,) if allow_notconv else ())
     return x, [st[b].as_dict() for b in range(B)]
+
+
+def solve_batch_topk(graph: Graph, seed_ptr, seeds, k=100, seed_w=None, d=0.85, tol=1e-6,
+                     precision="fp32", normalize=True, max_rounds=0, tune=None, stream=None,
+                     allow_notconv=False):
+    """Batched personalised PageRank keeping the k largest entries of each
+    vector.  Returns (ids int32[B, k] with -1 padding, x float64[B, k], list of
+    per-vector stats dicts) as numpy arrays."""
+    seed_ptr = np.ascontiguousarray(seed_ptr, dtype=np.int64)
+    seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+    sw = None if seed_w is None else np.ascontiguousarray(seed_w, dtype=np.float64)
+    B = len(seed_ptr) - 1
+    ids = np.empty((max(B, 0), k), dtype=np.int32)
+    vals = np.empty((max(B, 0), k), dtype=np.float64)
+    o = make_opts(d, tol, precision, normalize, max_rounds, tune, 0)
+    st = (Stats * max(B, 1))()
+    rc = _lib.di_solve_batch_topk(graph.handle, B, _ptr(seed_ptr), _ptr(seeds), _ptr(sw),
+                                  ctypes.byref(o), int(k), _ptr(ids), _ptr(vals), st,
+                                  _stream(stream))
+    _check(rc, allow=(ENOTCONV,) if allow_notconv else ())
+    return ids, vals, [st[b].as_dict() for b in range(B)]
 
 
 def inject_update(old: Graph, new: Graph, F, H, d=0.85, stream=None):

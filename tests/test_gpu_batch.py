@@ -131,3 +131,47 @@ def test_batch_256_vectors_on_1m_graph(di):
         v = wl.seed_vector(g.n, seeds[ptr[b]:ptr[b + 1]])
         xs = oracle.power(g, D, 1e-11, v)["x"]
         assert _l1(x[b].cpu().numpy(), xs) <= stats[b]["err_bound_l1"] + 1e-6, b
+
+
+@pytest.mark.parametrize("normalize", [True, False])
+def test_batch_topk_is_the_top_of_the_full_result(di, c1, normalize):
+    """di_solve_batch_topk returns, per vector, the k largest entries of what
+    di_solve_batch returns in full (the same device arithmetic), largest first."""
+    g = c1
+    G = di.Graph(g)
+    ptr, seeds = wl.ppr_seed_sets(g.n, 10, 100, seed=14)
+    x, _ = di.solve_batch(G, ptr, seeds, d=D, tol=1e-11, precision="fp64", normalize=normalize)
+    ids, vals, st = di.solve_batch_topk(G, ptr, seeds, k=50, d=D, tol=1e-11, precision="fp64",
+                                        normalize=normalize)
+    xb = x.cpu().numpy()
+    assert ids.shape == (10, 50) and vals.shape == (10, 50)
+    for b in range(10):
+        assert st[b]["residual_l1"] < 1e-11
+        assert np.all(np.diff(vals[b]) <= 0)
+        np.testing.assert_allclose(vals[b], np.sort(xb[b])[::-1][:50], rtol=1e-13, atol=0)
+        np.testing.assert_allclose(xb[b][ids[b]], vals[b], rtol=1e-13, atol=0)
+        assert len(set(ids[b].tolist())) == 50
+
+
+def test_batch_topk_pads_short_vectors(di):
+    """A seed on a dangling leaf of an out-star keeps all its fluid: one
+    non-zero entry, the rest of the k slots padded with -1 / 0."""
+    g = wl.out_star(10)
+    G = di.Graph(g)
+    ptr = np.array([0, 1, 2], np.int64)
+    seeds = np.array([3, 0], np.int32)
+    ids, vals, _ = di.solve_batch_topk(G, ptr, seeds, k=20, d=D, tol=1e-13, precision="fp64")
+    assert ids[0, 0] == 3 and abs(vals[0, 0] - 1.0) < 1e-15
+    assert np.all(ids[0, 1:] == -1) and np.all(vals[0, 1:] == 0.0)
+    # seed on the centre: the centre and its 10 leaves, then padding
+    assert np.all(ids[1, :11] >= 0) and np.all(ids[1, 11:] == -1)
+    xs = oracle.dense_exact(g, D, wl.seed_vector(g.n, [0]))[1]
+    np.testing.assert_allclose(vals[1, :11], xs[ids[1, :11]], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("k", [0, 1025])
+def test_batch_topk_rejects_bad_k(di, c1, k):
+    G = di.Graph(c1)
+    with pytest.raises(di.DiError) as e:
+        di.solve_batch_topk(G, np.array([0, 1], np.int64), np.array([5], np.int32), k=k)
+    assert e.value.status == di.EINVAL
