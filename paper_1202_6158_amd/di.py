@@ -346,17 +346,22 @@ def diffuse_round(graph: Graph, F, H, theta: float, d=0.85, stream=None):
 
 def solve_batch(graph: Graph, seed_ptr, seeds, seed_w=None, d=0.85, tol=1e-6, precision="fp32",
                 normalize=True, max_rounds=0, tune=None, out=None, stream=None,
-                allow_notconv=False):
+                allow_notconv=False, host=False):
     """Batched personalised PageRank.  seed_ptr int64[B+1], seeds int32, seed_w
     float64 or None (host arrays).  Returns (x: torch cuda float64[B, n],
-    list of per-vector stats dicts)."""
+    list of per-vector stats dicts); host=True returns x as a numpy array
+    (the library copies each group of vectors back)."""
     torch = _torch()
     seed_ptr = np.ascontiguousarray(seed_ptr, dtype=np.int64)
     seeds = np.ascontiguousarray(seeds, dtype=np.int32)
     sw = None if seed_w is None else np.ascontiguousarray(seed_w, dtype=np.float64)
     B = len(seed_ptr) - 1
-    x = out if out is not None else torch.empty((B, graph.n), dtype=torch.float64, device="cuda")
-    o = make_opts(d, tol, precision, normalize, max_rounds, tune, DEVICE_PTRS)
+    if host:
+        x = out if out is not None else np.empty((B, graph.n), dtype=np.float64)
+    else:
+        x = out if out is not None else torch.empty((B, graph.n), dtype=torch.float64,
+                                                    device="cuda")
+    o = make_opts(d, tol, precision, normalize, max_rounds, tune, 0 if host else DEVICE_PTRS)
     st = (Stats * max(B, 1))()
     rc = _lib.di_solve_batch(graph.handle, B, _ptr(seed_ptr), _ptr(seeds), _ptr(sw),
                              ctypes.byref(o), _ptr(x), st, _stream(stream))

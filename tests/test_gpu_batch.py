@@ -153,6 +153,20 @@ def test_batch_topk_is_the_top_of_the_full_result(di, c1, normalize):
         assert len(set(ids[b].tolist())) == 50
 
 
+def test_batch_with_host_output(di, c1):
+    """x as a host array: the library copies each group back; same result as
+    the device output."""
+    g = c1
+    G = di.Graph(g)
+    ptr, seeds = wl.ppr_seed_sets(g.n, 5, 100, seed=15)
+    xh, sh = di.solve_batch(G, ptr, seeds, d=D, tol=1e-11, precision="fp64", host=True)
+    xd, sd = di.solve_batch(G, ptr, seeds, d=D, tol=1e-11, precision="fp64")
+    assert isinstance(xh, np.ndarray) and xh.shape == (5, g.n)
+    for b in range(5):
+        assert abs(sh[b]["rounds"] - sd[b]["rounds"]) <= 1
+        assert _l1(xh[b], xd[b].cpu().numpy()) <= 1e-13
+
+
 def test_batch_topk_pads_short_vectors(di):
     """A seed on a dangling leaf of an out-star keeps all its fluid: one
     non-zero entry, the rest of the k slots padded with -1 / 0."""
