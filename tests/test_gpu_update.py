@@ -129,3 +129,27 @@ def test_update_at_one_million_nodes(di):
     xp, sp = di.power_solve(G1, d=D, tol=1e-10, precision="fp64")
     l1 = float(torch.sum(torch.abs(x - xp)).item())
     assert l1 <= st["err_bound_l1"] + sp["err_bound_l1"] + 1e-6
+
+
+@pytest.mark.parametrize("prec,tol,eps", [("fp64", 1e-11, 1e-12), ("fp32", 1e-8, 1e-6)])
+def test_successive_updates(di, prec, tol, eps):
+    """On-line use: five successive changes of 1% of the rows, each injected
+    into the state the previous one left and resumed.  The final result is
+    within its bound of the exact limit of the last graph, and Theorem 1 holds
+    for it on the final state."""
+    g = wl.recipe("pagerank-10k")
+    graphs = [g]
+    for k in range(5):
+        graphs.append(wl.modify_graph(graphs[-1], 0.01, seed=200 + k))
+    Gs = [di.Graph(x) for x in graphs]
+    F, H = _state(di, Gs[0], g, prec, tol)
+    for k in range(5):
+        di.inject_update(Gs[k], Gs[k + 1], F, H, d=D)
+        x, st = di.solve(Gs[k + 1], d=D, tol=tol, precision=prec, state=(F, H))
+        assert st["residual_l1"] < tol
+    last = graphs[-1]
+    xs = oracle.limit(last, D, tol=1e-14)
+    assert float(np.abs(x.cpu().numpy() - xs).sum()) <= st["err_bound_l1"] + eps
+    Hn, Fn = H.cpu().numpy(), F.cpu().numpy().astype(np.float64)
+    PH = oracle.transition_sparse(last) @ Hn
+    assert np.abs(Hn + Fn - ((1 - D) / last.n + D * PH)).sum() < (1e-12 if prec == "fp64" else 1e-6)
