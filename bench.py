@@ -247,10 +247,11 @@ def bench_ppr_batch(di, G, g, args):
             "frac_of_hbm_peak": abytes / t / 1e9 / HBM_PEAK_GBS}
 
 
-def bench_update(di, G, g, args):
+def bench_update(di, G, g, args, tune=None):
     """Graph update (Section 3.3): 1% of the nodes get new out-link lists;
     the converged state of the old graph plus the injected fluid d(P'-P)H is
-    resumed on the new graph, against a fresh solve of the new graph."""
+    resumed on the new graph, against a fresh solve of the new graph.  Every
+    solve here uses the knobs tuned on the original graph (tune)."""
     import numpy as np
     import torch
     import workloads as wl
@@ -261,40 +262,51 @@ def bench_update(di, G, g, args):
     for _ in range(reps):
         F = torch.full((g.n,), (1 - args.d) / g.n, dtype=dt, device="cuda")
         H = torch.zeros(g.n, dtype=torch.float64, device="cuda")
-        di.solve(G, d=args.d, tol=args.tol, precision=args.precision, state=(F, H))
+        di.solve(G, d=args.d, tol=args.tol, precision=args.precision, state=(F, H), tune=tune)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         di.inject_update(G, G1, F, H, d=args.d)
-        _, st_u = di.solve(G1, d=args.d, tol=args.tol, precision=args.precision, state=(F, H))
+        _, st_u = di.solve(G1, d=args.d, tol=args.tol, precision=args.precision, state=(F, H),
+                           tune=tune)
         torch.cuda.synchronize()
         t_upd.append(time.perf_counter() - t0)
         t0 = time.perf_counter()
-        _, st_f = di.solve(G1, d=args.d, tol=args.tol, precision=args.precision)
+        _, st_f = di.solve(G1, d=args.d, tol=args.tol, precision=args.precision, tune=tune)
         torch.cuda.synchronize()
         t_fresh.append(time.perf_counter() - t0)
     # On-line use: a stream of small changes (0.1% of the nodes each), every
     # one injected into the state left by the previous one and resumed.
     steps, frac = 10, 0.001
-    gs, Gs = [g], [G]
+    gs, Gs, t_setup = [g], [G], []
     for k in range(steps):
         gs.append(wl.modify_graph(gs[-1], frac, seed=100 + k))
         Gs.append(di.Graph(gs[-1]))
+        # one-off per graph, like its residency: the window tables of its first solve
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        di.solve(Gs[-1], d=args.d, tol=args.tol, precision=args.precision, tune=tune,
+                 max_rounds=1, allow_notconv=True)
+        torch.cuda.synchronize()
+        t_setup.append(time.perf_counter() - t0)
     F = torch.full((g.n,), (1 - args.d) / g.n, dtype=dt, device="cuda")
     H = torch.zeros(g.n, dtype=torch.float64, device="cuda")
-    di.solve(G, d=args.d, tol=args.tol, precision=args.precision, state=(F, H))
-    t_step, l_step, r_step = [], [], []
+    di.solve(G, d=args.d, tol=args.tol, precision=args.precision, state=(F, H), tune=tune)
+    t_step, t_inj, l_step, r_step = [], [], [], []
     for k in range(steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         di.inject_update(Gs[k], Gs[k + 1], F, H, d=args.d)
+        torch.cuda.synchronize()  # to time the injection apart (the call itself does not wait)
+        t_inj.append(time.perf_counter() - t0)
         x_u, st_k = di.solve(Gs[k + 1], d=args.d, tol=args.tol, precision=args.precision,
-                             state=(F, H))
+                             state=(F, H), tune=tune)
         torch.cuda.synchronize()
         t_step.append(time.perf_counter() - t0)
         l_step.append(st_k["edges_diffused"])
         r_step.append(st_k["rounds"])
     t0 = time.perf_counter()
-    x_f, st_ff = di.solve(Gs[-1], d=args.d, tol=args.tol, precision=args.precision)
+    x_f, st_ff = di.solve(Gs[-1], d=args.d, tol=args.tol, precision=args.precision,
+                         tune=tune)
     torch.cuda.synchronize()
     t_ff = time.perf_counter() - t0
     l1 = float(torch.sum(torch.abs(x_u - x_f)).item())
@@ -306,6 +318,8 @@ def bench_update(di, G, g, args):
             "update_residual_l1": st_u["residual_l1"],
             "stream": {"steps": steps, "changed_fraction_per_step": frac,
                        "mean_update_ms": 1e3 * float(np.mean(t_step)),
+                       "mean_inject_ms": 1e3 * float(np.mean(t_inj)),
+                       "mean_graph_setup_ms": 1e3 * float(np.mean(t_setup)),
                        "max_update_ms": 1e3 * max(t_step),
                        "mean_update_links": float(np.mean(l_step)),
                        "mean_update_rounds": float(np.mean(r_step)),
@@ -556,7 +570,9 @@ def main():
     if args.section:
         part = {"ppr": lambda: bench_ppr_batch(di, G, g, args),
                 "serve": lambda: bench_serve(di, args),
-                "update": lambda: bench_update(di, G, g, args),
+                "update": lambda: bench_update(di, G, g, args, None if args.no_autotune else
+                                               di.autotune(G, "solve", d=args.d, tol=args.tol,
+                                                           precision=args.precision)[0]),
                 "replay": lambda: bench_paper_replay(di, args)}[args.section]()
         print(json.dumps({"section": args.section, "result": part}), flush=True)
         return
@@ -662,7 +678,8 @@ def main():
     if not args.no_ppr:
         out["ppr_batch"] = bench_ppr_batch(di, G, g, args)
     if not args.no_update:
-        out["update"] = bench_update(di, G, g, args)
+        out["update"] = bench_update(di, G, g, args, fixed if fixed is not None else
+                                     (best if tune_info is not None else None))
     if not args.no_replay:
         out["paper_replay"] = bench_paper_replay(di, args)
     if not args.no_serve:

@@ -203,7 +203,8 @@ di_status di_diffuse_round(const di_graph* g, int32_t precision, double d, doubl
  * H + F = F_0 + d P' H holds (Theorem 1 for P'), and di_solve on g_new with
  * DI_RESUME and this state continues to the solution of X = d P' X + F_0
  * (Theorem 4).  The injected fluid may be negative: rounds take nodes on
- * |F_i|, the residual is ||F||_1.  DI_EINVAL if n differs.
+ * |F_i|, the residual is ||F||_1.  F is updated in the order of `stream`
+ * (the call does not wait for it).  DI_EINVAL if n differs.
  */
 di_status di_inject_update(const di_graph* g_old, const di_graph* g_new, int32_t precision,
                            double d, void* F, const double* H, void* stream);

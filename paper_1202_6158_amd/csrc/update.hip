@@ -56,18 +56,22 @@ template <typename T>
 void inject(const Graph* g0, const Graph* g1, double d, T* F, const double* H, hipStream_t s) {
   const int64_t n = g1->n;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 8192));
-  DevBuf delta;
-  delta.alloc(n * 8);
-  DI_HIP(hipMemsetAsync(delta.p, 0, n * 8, s));
+  // stream-ordered scratch: no device-wide synchronisation per update
+  double* delta = nullptr;
+  DI_HIP(hipMallocAsync(reinterpret_cast<void**>(&delta), n * 8, s));
+  DI_HIP(hipMemsetAsync(delta, 0, n * 8, s));
   k_inject_rows<<<grid, kBlock, 0, s>>>(
       n, g0->row_ptr.as<int64_t>(), g0->col.as<int32_t>(),
       g0->weighted ? g0->w.as<double>() : nullptr, g1->row_ptr.as<int64_t>(),
-      g1->col.as<int32_t>(), g1->weighted ? g1->w.as<double>() : nullptr, H,
-      delta.as<double>());
-  DI_HIP(hipGetLastError());
-  k_inject_apply<T><<<grid, kBlock, 0, s>>>(n, d, delta.as<double>(), F);
-  DI_HIP(hipGetLastError());
-  DI_HIP(hipStreamSynchronize(s));
+      g1->col.as<int32_t>(), g1->weighted ? g1->w.as<double>() : nullptr, H, delta);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    k_inject_apply<T><<<grid, kBlock, 0, s>>>(n, d, delta, F);
+    e = hipGetLastError();
+  }
+  (void)hipFreeAsync(delta, s);
+  DI_HIP(e);
+  // F is a device output: ready in stream order, no host wait
 }
 
 }  // namespace
