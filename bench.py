@@ -580,6 +580,7 @@ def main():
     # ---- autotuner: the knobs every later solve on this graph uses
     tune_info = None
     fixed = None
+    solve_tune = None  # the knobs the solves below use (also the update section's)
     if args.tune:
         sc, c, wl_, th = args.tune.split(":")
         fixed = di.make_tune(sc, float(c), int(wl_), threads=int(th))
@@ -587,6 +588,7 @@ def main():
     elif not args.no_autotune:
         t0 = time.perf_counter()
         best, trials = di.autotune(G, "solve", d=args.d, tol=args.tol, precision=args.precision)
+        solve_tune = best
         ok = [t for t in trials if t["status"] == 0]
         tune_info = {"best": di.tune_dict(best), "candidates": len(trials),
                      "default_ms": 1e3 * trials[0]["seconds"],
@@ -678,8 +680,7 @@ def main():
     if not args.no_ppr:
         out["ppr_batch"] = bench_ppr_batch(di, G, g, args)
     if not args.no_update:
-        out["update"] = bench_update(di, G, g, args, fixed if fixed is not None else
-                                     (best if tune_info is not None else None))
+        out["update"] = bench_update(di, G, g, args, fixed if fixed is not None else solve_tune)
     if not args.no_replay:
         out["paper_replay"] = bench_paper_replay(di, args)
     if not args.no_serve:
