@@ -21,24 +21,89 @@ namespace {
 // out-links (and weights) are the same in both graphs contributes nothing, so
 // only the changed rows push, +H_i p'(j,i) to the new children and
 // -H_i p(j,i) to the old ones (fp64 atomics; a change touches few rows).
+// Each block takes kBlock consecutive rows and compares the links of those
+// with equal degree as one concatenated range (consecutive threads read
+// consecutive links), flagging in LDS the rows where a link or weight differs;
+// the pushes of the flagged rows are then spread over the block the same way,
+// so a changed hub row does not serialise on one thread.
 __global__ __launch_bounds__(kBlock) void k_inject_rows(
     int64_t n, const int64_t* __restrict__ rp0, const int32_t* __restrict__ c0,
     const double* __restrict__ w0, const int64_t* __restrict__ rp1,
     const int32_t* __restrict__ c1, const double* __restrict__ w1,
     const double* __restrict__ H, double* __restrict__ delta) {
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-    const double h = H[i];
-    if (h == 0.0) continue;
-    const int64_t a0 = rp0[i], b0 = rp0[i + 1], a1 = rp1[i], b1 = rp1[i + 1];
-    bool same = b0 - a0 == b1 - a1 && (w0 == nullptr) == (w1 == nullptr);
-    for (int64_t k = 0; same && k < b0 - a0; ++k)
-      same = c0[a0 + k] == c1[a1 + k] && (!w0 || w0[a0 + k] == w1[a1 + k]);
-    if (same) continue;
-    for (int64_t e = a1; e < b1; ++e)
-      atomicAdd(&delta[c1[e]], h * (w1 ? w1[e] : 1.0 / (double)(b1 - a1)));
-    for (int64_t e = a0; e < b0; ++e)
-      atomicAdd(&delta[c0[e]], -h * (w0 ? w0[e] : 1.0 / (double)(b0 - a0)));
+  __shared__ long long s_off[kBlock];  // exclusive prefix of the links each row compares
+  __shared__ long long s_a0[kBlock], s_a1[kBlock];
+  __shared__ int s_diff[kBlock];
+  __shared__ double s_h[kBlock];
+  __shared__ long long s_n1[kBlock];  // new out-degree of a flagged row
+  __shared__ long long s_scr[kBlock / 64];
+  const int t = threadIdx.x;
+  const bool same_kind = (w0 == nullptr) == (w1 == nullptr);
+  for (int64_t r0 = (int64_t)blockIdx.x * kBlock; r0 < n; r0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t r = r0 + t;
+    double h = 0.0;
+    int64_t a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+    int diff = 0;
+    long long len = 0;
+    if (r < n) {
+      h = H[r];
+      a0 = rp0[r];
+      b0 = rp0[r + 1];
+      a1 = rp1[r];
+      b1 = rp1[r + 1];
+      if (h != 0.0) {  // a row with no history pushes nothing either way
+        if (b0 - a0 != b1 - a1 || !same_kind) diff = 1;
+        else len = b0 - a0;
+      }
+    }
+    long long total = 0;
+    const long long off = block_exscan<kBlock>(len, s_scr, &total);
+    s_off[t] = off;
+    s_a0[t] = a0;
+    s_a1[t] = a1;
+    s_diff[t] = diff;
+    __syncthreads();
+    for (long long q = t; q < total; q += kBlock) {
+      // the row of comparison q: the last j with s_off[j] <= q (it has links)
+      int lo = 0, hi = kBlock - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= q) lo = mid;
+        else hi = mid - 1;
+      }
+      const long long k = q - s_off[lo];
+      const int64_t e0 = s_a0[lo] + k, e1 = s_a1[lo] + k;
+      if (c0[e0] != c1[e1] || (w0 && w0[e0] != w1[e1])) s_diff[lo] = 1;
+    }
+    __syncthreads();
+    // pushes of the flagged rows: new links first (+), then old links (-)
+    const long long plen = (r < n && h != 0.0 && s_diff[t]) ? (b1 - a1) + (b0 - a0) : 0;
+    long long ptotal = 0;
+    const long long poff = block_exscan<kBlock>(plen, s_scr, &ptotal);
+    s_off[t] = poff;
+    s_h[t] = h;
+    s_n1[t] = b1 - a1;
+    s_a0[t] = a0;
+    s_a1[t] = a1;
+    s_diff[t] = (int)(b0 - a0);  // now: old out-degree
+    __syncthreads();
+    for (long long q = t; q < ptotal; q += kBlock) {
+      int lo = 0, hi = kBlock - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= q) lo = mid;
+        else hi = mid - 1;
+      }
+      const long long k = q - s_off[lo], n1 = s_n1[lo];
+      if (k < n1) {
+        const int64_t e = s_a1[lo] + k;
+        unsafeAtomicAdd(&delta[c1[e]], s_h[lo] * (w1 ? w1[e] : 1.0 / (double)n1));
+      } else {
+        const int64_t e = s_a0[lo] + (k - n1);
+        unsafeAtomicAdd(&delta[c0[e]], -s_h[lo] * (w0 ? w0[e] : 1.0 / (double)s_diff[lo]));
+      }
+    }
+    __syncthreads();  // the LDS arrays are reused by the next rows
   }
 }
 
