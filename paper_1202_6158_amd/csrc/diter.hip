@@ -221,6 +221,31 @@ __device__ __forceinline__ double node_score(double f, int dg, int indeg) {
   return f;
 }
 
+// Score sum and count of the nodes holding fluid in a resumed state: the
+// first round of a resumed solve takes c times their mean score as its
+// threshold (the rule of every later round) instead of 0, so that it does not
+// take every node that kept a trace of fluid.  out[0..1] must start at zero.
+template <typename T, int SCHED>
+__global__ __launch_bounds__(kBlock) void k_resume_scores(DiArgs<T> a, double* __restrict__ out) {
+  __shared__ double s_red[kBlock / 64];
+  double ssc = 0.0, nnz = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double f = fabs((double)a.F[i]);
+    if (f > 0.0) {
+      const int dg = SCHED != DI_SCHED_MEAN ? a.deg[i] : -1;
+      ssc += node_score<SCHED>(f, dg, SCHED == DI_SCHED_OP ? a.indeg[i] : 0);
+      nnz += 1.0;
+    }
+  }
+  ssc = block_sum(ssc, s_red);
+  nnz = block_sum(nnz, s_red);
+  if (threadIdx.x == 0) {
+    unsafeAtomicAdd(&out[0], ssc);
+    unsafeAtomicAdd(&out[1], nnz);
+  }
+}
+
 // In-place exclusive scan of arr[0..n) in LDS (NT threads); returns the total.
 template <int NT>
 __device__ long long lds_exscan(int32_t* arr, int n, long long* scr) {
@@ -1147,6 +1172,21 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   }
   LaunchTimer lt(s, (o->flags & DI_TIMING) != 0);
   EventTimer timer(s);
+  if (resume) {
+    // first threshold from the resumed fluid (the flush scratch is cleared
+    // again before the flush)
+    double* acc = ws->flacc.as<double>();
+    double* hacc = ws->hctl2.as<double>();
+    DI_HIP(hipMemsetAsync(acc, 0, 2 * sizeof(double), s));
+    const dim3 gr(grid_for(g->n, 128));
+    if (tp.sched == DI_SCHED_OP2) k_resume_scores<T, DI_SCHED_OP2><<<gr, kBlock, 0, s>>>(a, acc);
+    else if (tp.sched == DI_SCHED_OP) k_resume_scores<T, DI_SCHED_OP><<<gr, kBlock, 0, s>>>(a, acc);
+    else k_resume_scores<T, DI_SCHED_MEAN><<<gr, kBlock, 0, s>>>(a, acc);
+    DI_HIP(hipGetLastError());
+    DI_HIP(hipMemcpyAsync(hacc, acc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    DI_HIP(hipStreamSynchronize(s));
+    if (hacc[1] > 0.0 && std::isfinite(hacc[0])) a.theta0 = tp.c * hacc[0] / hacc[1];
+  }
   k_init<T><<<dim3(grid_for(g->n, 2048), 1), kBlock, 0, s>>>(a, vdev, resume ? 1 : 0, 0);
   DI_HIP(hipGetLastError());
   run_rounds(a, ws, tp.sched, tp.check_every, s, &lt);
