@@ -48,6 +48,19 @@ def test_transition_matrix_by_hand():
     np.testing.assert_allclose(P, expect, atol=0)
 
 
+def test_sparse_transition_by_hand_and_against_dense():
+    """The sparse P used by the update and replay helpers: the same hand-worked
+    matrix (repeated link, self-loop, dangling column), and equal to the dense
+    one on random graphs with repeats and self-loops."""
+    g = wl.from_edges(3, [0, 0, 0, 1], [1, 2, 2, 1])
+    expect = np.array([[0, 0, 0], [1 / 3, 1, 0], [2 / 3, 0, 0]])
+    np.testing.assert_allclose(oracle.transition_sparse(g).toarray(), expect, atol=0)
+    for seed in (1, 2, 3):
+        g = wl.random_small(120, 700, seed=seed)
+        np.testing.assert_allclose(oracle.transition_sparse(g).toarray(),
+                                   oracle.transition_dense(g), rtol=1e-15, atol=0)
+
+
 @pytest.mark.parametrize("n", [1, 2, 7, 50])
 def test_cycle_uniform(n):
     g = wl.cycle(n) if n > 1 else wl.from_edges(1, [0], [0])
