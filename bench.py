@@ -248,7 +248,7 @@ def bench_ppr_batch(di, G, g, args):
 
 
 def bench_update(di, G, g, args, tune=None):
-    """Graph update (Section 3.3): 1% of the nodes get new out-link lists;
+    """Graph update (Section 3.2): 1% of the nodes get new out-link lists;
     the converged state of the old graph plus the injected fluid d(P'-P)H is
     resumed on the new graph, against a fresh solve of the new graph.  Every
     solve here uses the knobs tuned on the original graph (tune)."""
@@ -331,7 +331,7 @@ def bench_update(di, G, g, args, tune=None):
 
 
 def bench_paper_replay(di, args):
-    """The paper's six simulation scenarios (Section 5): links diffused by the
+    """The paper's six simulation scenarios (Section 4.1): links diffused by the
     D-iteration (its elementary steps) and by the power iteration (L per
     product), device times, fp64, same stop rule."""
     import workloads as wl

@@ -8,7 +8,7 @@
  *
  * for a non-negative N x N matrix P whose non-zero columns sum to one (column
  * i = the out-links of node i, P[j][i] = p(j,i)); zero columns (dangling
- * nodes) are allowed and are NOT completed (Section 3.4).  V is a normalised
+ * nodes) are allowed and are NOT completed (Section 3.3).  V is a normalised
  * non-negative vector (uniform for PageRank, a seed set for personalised
  * PageRank), 0 <= d < 1.
  *
@@ -19,7 +19,7 @@
  * round, every node whose fluid reaches an adaptive threshold (the threshold
  * variant of Section 4.2), all at once.  Theorem 2 makes ||F||_1 the stopping
  * residual.  The result is x = (H + F) / ||H + F||_1 (renormalisation of
- * Section 3.4), or the unnormalised H + F.
+ * Section 3.3), or the unnormalised H + F.
  *
  * Conventions for every entry point:
  *  - Nothing throws and nothing aborts.  Each call returns a di_status; on
@@ -194,7 +194,7 @@ di_status di_diffuse_round(const di_graph* g, int32_t precision, double d, doubl
                            void* stream);
 
 /*
- * Graph update (the updating equation of Section 3.3).  The graph changes
+ * Graph update (the updating equation of Section 3.2).  The graph changes
  * from P (g_old) to P' (g_new), both with the same n, while a solve on P is
  * under way (or done) with device state F (float[n] for DI_FP32_FLUID,
  * double[n] for DI_FP64) and H (double[n]).  Adds d (P' - P) H to F (only
@@ -212,7 +212,11 @@ di_status di_inject_update(const di_graph* g_old, const di_graph* g_new, int32_t
 /* ---------------------------------------------------------------- batches */
 
 /*
- * Personalised PageRank for B seed sets on one graph.  Seed set b is
+ * Personalised PageRank for B seed sets on one graph: B independent D-iteration
+ * solves of X = dPX + (1-d)V_b, V_b being the personalisation vector of
+ * Section 2.1 (the initial condition F_0 = (1-d)V_b of Section 2.2), each
+ * stopped by Theorem 2's residual ||F_b||_1 < tol (Section 3.1) and
+ * renormalised as Section 3.3 says when P has dangling columns.  Seed set b is
  * seeds[seed_ptr[b] .. seed_ptr[b+1]) (non-empty, ids in [0,n), no repeats);
  * V_b puts weight seed_w[k] on seeds[k] (seed_w NULL = uniform over the set;
  * otherwise each set's weights must sum to 1 within 1e-9).  opts applies to
@@ -225,7 +229,9 @@ di_status di_solve_batch(const di_graph* g, int32_t B, const int64_t* seed_ptr,
                          double* x, di_stats* stats, void* stream);
 
 /*
- * di_solve_batch keeping only each vector's topk largest entries (the B x n
+ * di_solve_batch keeping only each vector's topk largest entries (the
+ * same solves as di_solve_batch: V_b of Section 2.1, stop of Theorem 2 in
+ * Section 3.1, renormalisation of Section 3.3; the B x n
  * result is never formed outside the device): top_ids int32[B*topk] holds
  * the node ids, largest value first, ties by id, and -1 past the vector's
  * last non-zero entry; top_x double[B*topk] the values (normalised as
@@ -258,7 +264,7 @@ typedef struct di_tune_trial {
  * then the best pair at larger and smaller windows, one size at a time in
  * each direction while the time improves, then the winner with 1024-thread
  * workgroups.  Any schedule converges to the same limit (the order
- * independence of Section 2), so only speed is compared.
+ * independence of Sections 2.2 and 3.1), so only speed is compared.
  * The default knobs (mean, c = 1) run first; every other candidate gets at
  * most four times their rounds (at least 64, at most opts->max_rounds when
  * set) and is discarded if it does not converge within them.
@@ -308,12 +314,19 @@ typedef struct di_server_metrics {
   double p50_latency_s, p99_latency_s, qps;
 } di_server_metrics;
 
-/* Create a server with its own scheduler thread and HIP stream. */
+/* Create a server of personalised PageRank requests: each request is a
+   D-iteration solve of X = dPX + (1-d)V with V its seed set (the
+   personalisation vector of Section 2.1), stopped by Theorem 2's residual
+   ||F||_1 < tol (Section 3.1) and renormalised as in Section 3.3.  The server
+   runs one scheduler thread and HIP stream per resident graph. */
 di_status di_server_create(const di_server_opts* opts, di_server** out);
 /* Register a resident graph (not copied; must outlive the server). */
 di_status di_server_add_graph(di_server* s, const di_graph* g, int32_t* graph_id);
-/* Enqueue a PPR request (thread-safe, non-blocking).  seeds (and w, NULL =
-   uniform) are host arrays copied at submit.  DI_EINVAL on bad input,
+/* Enqueue a PPR request (thread-safe, non-blocking): V puts weight w[k] on
+   seeds[k] (the personalisation vector of Section 2.1; w NULL = uniform over
+   the seeds), d is the damping factor and the request stops when its
+   ||F||_1 < tol (Theorem 2, Section 3.1).  seeds (and w) are host arrays
+   copied at submit.  DI_EINVAL on bad input,
    DI_ENOMEM if one request can never fit the budget. */
 di_status di_server_submit(di_server* s, int32_t graph_id, int32_t n_seeds, const int32_t* seeds,
                            const double* w, double d, double tol, uint64_t* req_id);

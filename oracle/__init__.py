@@ -5,20 +5,20 @@ Plain, slow, obviously-correct fp64 implementations written from the paper
 
 * :func:`dense_exact` -- the plain definition of the limit, Y = (1-d)(I-dP)^{-1}V
   (Section 2.2: S_inf = X), by LU on the dense matrix; ``x* = Y/||Y||_1``
-  (Section 3.4: renormalisation when P has dangling columns).
+  (Section 3.3: renormalisation when P has dangling columns).
 * :func:`completed_pagerank` -- the stationary vector of the completed matrix
   A = d Pbar + (1-d) V 1^t, whose zero columns are replaced by V (Section 2.1),
-  by eigen-decomposition; Section 3.4 states it equals ``x*``.
+  by eigen-decomposition; Section 3.3 states it equals ``x*``.
 * :func:`sparse_exact` -- the same definition by a sparse direct solve.
 * :func:`diter` -- the sequential D-iteration (ALGO-REF with the dangling rule,
-  Sections 2.2 and 3.4) in the orders of Section 4 (PER, RAND, MAX, threshold
+  Sections 2.2 and 3.3) in the orders of Section 4 (PER, RAND, MAX, threshold
   sweeps, OP, OP2), in C.
 * :func:`set_step` / :func:`diter_sets` -- diffusion of a whole threshold set at
   once (J_{i_n} replaced by the selector of a set), in C.
 * :func:`power` -- MAT-ITER X_{n+1} = dPX_n + (1-d)V from X_0 = 0 (Sections 2.1, 4),
   in C.
 * :func:`inject_update` -- the fluid a graph update injects, F' = F + d(P'-P)H
-  (updating equation, Section 3.3); :func:`set_step_signed` -- a set step on
+  (updating equation, Section 3.2); :func:`set_step_signed` -- a set step on
   fluid of either sign (|F_i| against the threshold), in numpy.
 * :func:`dense_exact_weighted` / :func:`set_step_weighted` -- the limit and a set
   step for a weighted P (any column-stochastic P of Section 2.1), in numpy.
@@ -245,7 +245,7 @@ def transition_sparse(g):
 
 
 def inject_update(g_old, g_new, d: float, F, H):
-    """Updating equation (Section 3.3): when P becomes P' with the state (F, H)
+    """Updating equation (Section 3.2): when P becomes P' with the state (F, H)
     of a D-iteration on P, the D-iteration continues on P' from
     F' = F + d (P' - P) H (Theorem 4: H + F' = F_0 + d P' H).  fp64."""
     H = np.asarray(H, dtype=np.float64)

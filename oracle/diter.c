@@ -11,7 +11,7 @@
  * unweighted graph p(j,i) = m_ij / outdeg(i), where m_ij counts the links
  * i -> j (repeated links and self-loops count with multiplicity).  A node with
  * no out-link (dangling node) has a zero column and is NOT completed
- * (Section 3.4).  The solve targets X = dPX + (1-d)V, 0 <= d < 1.
+ * (Section 3.3).  The solve targets X = dPX + (1-d)V, 0 <= d < 1.
  *
  * State (Section 2.2, fluid and history recurrences):
  *   F_0 = (1-d) V,  H_0 = 0.
@@ -20,7 +20,7 @@
  *                      else F_j += d * sent * p(j,i) for every child j.
  *   The running remaining-fluid scalar R starts at 1-d (for a normalised V)
  *   and loses (1-d)*sent per non-dangling diffusion and sent per dangling one
- *   (Section 3.4).
+ *   (Section 3.3).
  * Stop: when the freshly summed ||F||_1 drops below tol (Theorem 2 makes
  * ||F||_1/(1-d) the L1 distance of H to the limit on graphs without dangling
  * nodes, and an upper bound otherwise).
@@ -85,7 +85,7 @@ static uint64_t splitmix64(uint64_t x) {
 }
 
 /*
- * Sequential D-iteration (ALGO-REF with dangling nodes, Sections 2.2 and 3.4)
+ * Sequential D-iteration (ALGO-REF with dangling nodes, Sections 2.2 and 3.3)
  * in one of the orders above.  F and H are in/out: the caller initialises them
  * (F = (1-d)V, H = 0 for a fresh solve; any state satisfying Theorem 1 to
  * resume).  r0 is the initial running R.  c is the threshold factor of

@@ -1,7 +1,8 @@
 // Autotuner of the threshold schedule, threshold factor and window size.
 //
 // The D-iteration converges to the same limit whatever set of nodes each
-// round diffuses (the order independence of Section 2), so the knobs of the
+// round diffuses (any sequence I works, Section 2.2; Theorem 2 and the Lemma of
+// Section 3.1), so the knobs of the
 // threshold variant (Section 4.2, and the OP / OP2 scores of Section 4.3)
 // trade only speed: a low threshold diffuses more links per round and needs
 // fewer rounds, a high one wastes fewer links on small fluid.  Which side

@@ -4,7 +4,7 @@
 // every node whose score reaches the threshold theta_r (the threshold variant
 // of Section 4.2) is taken at once, H_i += F_i, F_i = 0, and its fluid is
 // pushed, d F_i p(j,i) to each child j.  Dangling nodes are taken like any
-// other but push nothing (Section 3.4).
+// other but push nothing (Section 3.3).
 //
 // The node set is cut into windows of 2^wlog consecutive ids; workgroup b owns
 // window b for the whole solve.  Launch r of k_round, in workgroup b:
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   //    round takes one set S (reading 5) even though pushes that stay inside
   //    the window are applied to its LDS copy at once.
   for (int q = tid; q < W; q += kRT) {
-    // Fluid may be signed after an update of the graph (Section 3.3): the
+    // Fluid may be signed after an update of the graph (Section 3.2): the
     // threshold and the residual use |F_i|.
     const double f = q < wn ? win[q] : 0.0, af = fabs(f);
     uint8_t st = 0;
@@ -723,7 +723,7 @@ __global__ __launch_bounds__(kBlock) void k_flush_reduce(DiArgs<T> a) {
   }
 }
 
-// x = (H + F) / sum(H + F)  (renormalisation of Section 3.4), or H + F.
+// x = (H + F) / sum(H + F)  (renormalisation of Section 3.3), or H + F.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_flush_write(DiArgs<T> a, double* __restrict__ x,
                                                         int normalize) {
@@ -1234,16 +1234,69 @@ __global__ __launch_bounds__(kBlock) void k_topk_hist(DiArgs<T> a, int shift, co
     if (h[k]) atomicAdd(&gh[k], h[k]);
 }
 
-// Candidates: every i whose key >> 9 is at least thr[y] (a key prefix of 23 bits).
+// Candidates of vector y: every i whose key >> 9 (a key prefix of 23 bits) is
+// at least thr[y].  Those at or above hi[y] (fewer than kk by the choice of
+// the thresholds) go to slots [0, kk); the rest, the entries of the
+// threshold's own bin, to slots [kk, cap).  Counts: hcount[y], ecount[y]
+// (the latter may exceed the room; the host then collects that vector again
+// with k_topk_all).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_topk_collect(DiArgs<T> a, const uint32_t* thr,
+                                                         const uint32_t* hi, int kk,
                                                          double* __restrict__ cval,
                                                          int32_t* __restrict__ cid,
-                                                         int32_t* __restrict__ ccount, int cap) {
+                                                         int32_t* __restrict__ hcount,
+                                                         int32_t* __restrict__ ecount, int cap) {
   const int y = blockIdx.y, vb = a.vmap[y];
   const T* F = a.F + (int64_t)vb * a.n;
   const double* H = a.H + (int64_t)vb * a.n;
-  const uint32_t t = thr[y];
+  const uint32_t t = thr[y], th = hi[y];
+  const int lane = threadIdx.x & 63;
+  for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < a.n; i0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = i0 + threadIdx.x;
+    double x = 0.0;
+    uint32_t key = 0;
+    if (i < a.n) {
+      x = H[i] + (double)F[i];
+      key = __float_as_uint((float)x) >> 9;
+    }
+    const bool take = i < a.n && key >= t;
+    const bool top = take && key >= th;
+    // one reservation per wave and class
+    const unsigned long long mt = __ballot(top), me = __ballot(take && !top);
+    if ((mt | me) == 0) continue;
+    int bt = 0, be = 0;
+    if (mt && lane == __ffsll((long long)mt) - 1) bt = atomicAdd(&hcount[y], __popcll(mt));
+    if (me && lane == __ffsll((long long)me) - 1) be = atomicAdd(&ecount[y], __popcll(me));
+    if (mt) bt = __shfl(bt, __ffsll((long long)mt) - 1, 64);
+    if (me) be = __shfl(be, __ffsll((long long)me) - 1, 64);
+    const unsigned long long below = (1ull << lane) - 1;
+    int pos = -1;
+    if (top) {
+      const int p = bt + __popcll(mt & below);
+      if (p < kk) pos = p;  // always: fewer than kk entries lie above the bin
+    } else if (take) {
+      const int p = be + __popcll(me & below);
+      if (p < cap - kk) pos = kk + p;
+    }
+    if (pos >= 0) {
+      cval[(int64_t)y * cap + pos] = x;
+      cid[(int64_t)y * cap + pos] = (int32_t)i;
+    }
+  }
+}
+
+// Every i of vector vmap[y] whose key >> 9 is at least t, into out[0..) in
+// any order (the caller sized out by the count the collection found).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_topk_all(DiArgs<T> a, int y, uint32_t t,
+                                                     double* __restrict__ oval,
+                                                     int32_t* __restrict__ oid,
+                                                     int32_t* __restrict__ count, int64_t room) {
+  const int vb = a.vmap[y];
+  const T* F = a.F + (int64_t)vb * a.n;
+  const double* H = a.H + (int64_t)vb * a.n;
+  const int lane = threadIdx.x & 63;
   for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < a.n; i0 += (int64_t)gridDim.x * kBlock) {
     const int64_t i = i0 + threadIdx.x;
     double x = 0.0;
@@ -1252,27 +1305,29 @@ __global__ __launch_bounds__(kBlock) void k_topk_collect(DiArgs<T> a, const uint
       x = H[i] + (double)F[i];
       take = (__float_as_uint((float)x) >> 9) >= t;
     }
-    // one reservation per wave
     const unsigned long long m = __ballot(take);
     if (m == 0) continue;
-    const int lane = threadIdx.x & 63;
     int base = 0;
-    if (lane == __ffsll((long long)m) - 1) base = atomicAdd(&ccount[y], __popcll(m));
+    if (lane == __ffsll((long long)m) - 1) base = atomicAdd(count, __popcll(m));
     base = __shfl(base, __ffsll((long long)m) - 1, 64);
     if (take) {
-      const int pos = base + __popcll(m & ((1ull << lane) - 1));
-      if (pos < cap) {
-        cval[(int64_t)y * cap + pos] = x;
-        cid[(int64_t)y * cap + pos] = (int32_t)i;
+      const int64_t p = base + __popcll(m & ((1ull << lane) - 1));
+      if (p < room) {
+        oval[p] = x;
+        oid[p] = (int32_t)i;
       }
     }
   }
 }
 
 // The kk largest entries of H+F of k vectors (a.vmap[0..k)) on the device:
-// a histogram of the fp32 key's top bits picks a threshold that at least kk
-// entries reach (refined by the next 11 bits when too many share its bin),
-// the entries above it are collected, and the host sorts that short list.
+// a histogram of the fp32 key's top bits picks a threshold bin that at least
+// kk entries reach (refined by the next 11 bits when too many share its bin);
+// the entries above that bin (fewer than kk) and those of the bin (as many as
+// the room holds) are collected, and the host sorts that short list.  A
+// vector whose threshold bin overflows the room (many equal or nearly equal
+// values) has all its candidates collected again into a buffer of their
+// exact count, so the result is exact in every case.
 template <typename T>
 class TopKT {
  public:
@@ -1283,10 +1338,10 @@ class TopKT {
     h_hist_.alloc((int64_t)cap * kTopBins * 4);
     par_.alloc(cap * 4);
     h_par_.alloc(cap * 4);
-    thr_.alloc(cap * 4);
-    h_thr_.alloc(cap * 4);
-    ccount_.alloc(cap * 4);
-    h_ccount_.alloc(cap * 4);
+    thr_.alloc(cap * 8);
+    h_thr_.alloc(cap * 8);
+    ccount_.alloc(cap * 8);
+    h_ccount_.alloc(cap * 8);
     cval_.alloc((int64_t)cap * kCap * 8);
     cid_.alloc((int64_t)cap * kCap * 4);
     h_cval_.alloc((int64_t)cap * kCap * 8);
@@ -1297,6 +1352,7 @@ class TopKT {
   // first, ties by node id; fewer when fewer entries are non-zero.
   void run(const DiArgs<T>& a, int k, int kk,
            std::vector<std::vector<std::pair<double, int32_t>>>& out, hipStream_t s) {
+    DI_REQUIRE(kk >= 1 && kk <= 1024, "top-k size out of range");
     const int gx = grid_for(a.n, 512);
     DI_HIP(hipMemsetAsync(hist_.p, 0, (int64_t)k * kTopBins * 4, s));
     k_topk_hist<T><<<dim3(gx, k), kBlock, 0, s>>>(a, 20, nullptr, hist_.as<int32_t>());
@@ -1305,7 +1361,7 @@ class TopKT {
     DI_HIP(hipStreamSynchronize(s));
     const int32_t* hh = h_hist_.as<int32_t>();
     int32_t* par = h_par_.as<int32_t>();
-    uint32_t* thr = h_thr_.as<uint32_t>();
+    uint32_t* thr = h_thr_.as<uint32_t>();  // [0, k): bin threshold, [k, 2k): above the bin
     bool refine = false;
     std::vector<int64_t> above(k, 0);
     for (int q = 0; q < k; ++q) {
@@ -1317,9 +1373,10 @@ class TopKT {
         cum += h[b];
       }
       // fewer than kk non-zero entries: take every non-zero one (bins >= 1)
-      par[q] = b >= 1 && cum + h[b] > kCap ? b : -1;
+      par[q] = b >= 1 && cum + h[b] > kCap - kk ? b : -1;
       above[q] = cum;
       thr[q] = (uint32_t)std::max(b, 1) << 11;  // key >> 9 >= b << 11  <=>  key >> 20 >= b
+      thr[k + q] = (uint32_t)(std::max(b, 1) + 1) << 11;
       if (par[q] >= 0) refine = true;
     }
     if (refine) {
@@ -1340,30 +1397,63 @@ class TopKT {
           cum += h[b];
         }
         thr[q] = ((uint32_t)par[q] << 11) | (uint32_t)b;
+        thr[k + q] = thr[q] + 1;
       }
     }
-    DI_HIP(hipMemcpyAsync(thr_.p, h_thr_.p, k * 4, hipMemcpyHostToDevice, s));
-    DI_HIP(hipMemsetAsync(ccount_.p, 0, k * 4, s));
-    k_topk_collect<T><<<dim3(gx, k), kBlock, 0, s>>>(a, thr_.as<uint32_t>(), cval_.as<double>(),
-                                                      cid_.as<int32_t>(), ccount_.as<int32_t>(),
-                                                      kCap);
+    DI_HIP(hipMemcpyAsync(thr_.p, h_thr_.p, 2 * k * 4, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemsetAsync(ccount_.p, 0, 2 * k * 4, s));
+    int32_t* dcount = ccount_.as<int32_t>();
+    k_topk_collect<T><<<dim3(gx, k), kBlock, 0, s>>>(a, thr_.as<uint32_t>(),
+                                                      thr_.as<uint32_t>() + k, kk,
+                                                      cval_.as<double>(), cid_.as<int32_t>(),
+                                                      dcount, dcount + k, kCap);
     DI_HIP(hipGetLastError());
-    DI_HIP(hipMemcpyAsync(h_ccount_.p, ccount_.p, k * 4, hipMemcpyDeviceToHost, s));
+    DI_HIP(hipMemcpyAsync(h_ccount_.p, ccount_.p, 2 * k * 4, hipMemcpyDeviceToHost, s));
     DI_HIP(hipMemcpyAsync(h_cval_.p, cval_.p, (int64_t)k * kCap * 8, hipMemcpyDeviceToHost, s));
     DI_HIP(hipMemcpyAsync(h_cid_.p, cid_.p, (int64_t)k * kCap * 4, hipMemcpyDeviceToHost, s));
     DI_HIP(hipStreamSynchronize(s));
-    const int32_t* cc = h_ccount_.as<int32_t>();
+    const int32_t* hc = h_ccount_.as<int32_t>();
+    const int32_t* ec = hc + k;
+    auto by_rank = [](const std::pair<double, int32_t>& x, const std::pair<double, int32_t>& y) {
+      return x.first > y.first || (x.first == y.first && x.second < y.second);
+    };
     out.assign(k, {});
     for (int q = 0; q < k; ++q) {
-      const int nc = std::min(cc[q], kCap);
       std::vector<std::pair<double, int32_t>>& v = out[q];
-      v.resize(nc);
-      for (int t = 0; t < nc; ++t)
-        v[t] = {h_cval_.as<double>()[(int64_t)q * kCap + t], h_cid_.as<int32_t>()[(int64_t)q * kCap + t]};
-      std::sort(v.begin(), v.end(), [](const auto& x, const auto& y) {
-        return x.first > y.first || (x.first == y.first && x.second < y.second);
-      });
-      if ((int)v.size() > kk) v.resize(kk);
+      if (hc[q] >= kk) {
+        set_error("internal top-k threshold inconsistent");
+        throw Fail{DI_EDEVICE};
+      }
+      if (ec[q] <= kCap - kk) {
+        const double* cv = h_cval_.as<double>() + (int64_t)q * kCap;
+        const int32_t* ci = h_cid_.as<int32_t>() + (int64_t)q * kCap;
+        for (int t = 0; t < hc[q]; ++t) v.push_back({cv[t], ci[t]});
+        for (int t = 0; t < ec[q]; ++t) v.push_back({cv[kk + t], ci[kk + t]});
+      } else {
+        // the threshold bin overflowed the room: every candidate, exactly
+        const int64_t total = (int64_t)hc[q] + ec[q];
+        DevBuf ov, oi, oc;
+        ov.alloc(total * 8);
+        oi.alloc(total * 4);
+        oc.alloc(4);
+        DI_HIP(hipMemsetAsync(oc.p, 0, 4, s));
+        k_topk_all<T><<<gx, kBlock, 0, s>>>(a, q, thr[q], ov.as<double>(), oi.as<int32_t>(),
+                                            oc.as<int32_t>(), total);
+        DI_HIP(hipGetLastError());
+        std::vector<double> hv(total);
+        std::vector<int32_t> hi(total);
+        DI_HIP(hipMemcpyAsync(hv.data(), ov.p, total * 8, hipMemcpyDeviceToHost, s));
+        DI_HIP(hipMemcpyAsync(hi.data(), oi.p, total * 4, hipMemcpyDeviceToHost, s));
+        DI_HIP(hipStreamSynchronize(s));
+        v.resize(total);
+        for (int64_t t = 0; t < total; ++t) v[t] = {hv[t], hi[t]};
+      }
+      if ((int)v.size() > kk) {
+        std::partial_sort(v.begin(), v.begin() + kk, v.end(), by_rank);
+        v.resize(kk);
+      } else {
+        std::sort(v.begin(), v.end(), by_rank);
+      }
     }
   }
 

@@ -1,4 +1,4 @@
-// Graph update: the fluid injection of the updating equation (Section 3.3).
+// Graph update: the fluid injection of the updating equation (Section 3.2).
 //
 // When P changes to P' after some rounds, the state (F, H) of the old solve
 // becomes a state of the new one by adding d (P' - P) H to the fluid: then

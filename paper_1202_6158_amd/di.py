@@ -189,6 +189,37 @@ def _ptr(a):
     return ctypes.c_void_p(a.data_ptr())
 
 
+def _check_device_tensor(t, name, dtype, numel):
+    """Raise ValueError unless t is a contiguous CUDA tensor of the given
+    dtype and element count (checked before any library call, so a wrong
+    tensor never reaches a kernel)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor (got %s)" % (name, type(t).__name__))
+    if not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must have dtype %s (got %s)" % (name, dtype, t.dtype))
+    if t.numel() != numel:
+        raise ValueError("%s must have %d elements (got %d)" % (name, numel, t.numel()))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def _check_host_array(a, name, numel):
+    """Raise ValueError unless a is a C-contiguous float64 numpy array of numel
+    elements."""
+    if not isinstance(a, np.ndarray):
+        raise ValueError("%s must be a numpy array with host=True" % name)
+    if a.dtype != np.float64 or a.size != numel or not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("%s must be a C-contiguous float64 array of %d elements" % (name, numel))
+
+
+def _fluid_dtype(precision):
+    torch = _torch()
+    return torch.float64 if PRECISION[precision] == FP64 else torch.float32
+
+
 TABLES = {"auto": 0, "lds": 1, "global": 2}
 
 
@@ -257,9 +288,11 @@ def _device_vec(v, n):
         return None
     torch = _torch()
     if isinstance(v, np.ndarray):
+        if v.size != n:
+            raise ValueError("v must have %d elements (got %d)" % (n, v.size))
         v = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).cuda()
-    assert v.dtype == torch.float64 and v.is_cuda and v.numel() == n
-    return v.contiguous()
+    _check_device_tensor(v, "v", torch.float64, n)
+    return v
 
 
 def _host_vec(v, n):
@@ -267,7 +300,8 @@ def _host_vec(v, n):
     if v is None:
         return None
     v = np.ascontiguousarray(v, dtype=np.float64)
-    assert v.shape == (n,)
+    if v.shape != (n,):
+        raise ValueError("v must have shape (%d,) (got %s)" % (n, v.shape))
     return v
 
 
@@ -283,6 +317,22 @@ def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=Tr
     bus) and returns x as a numpy array."""
     torch = _torch()
     n = graph.n
+    if precision not in PRECISION:
+        raise ValueError("unknown precision %r" % (precision,))
+    if state is not None:
+        if len(state) != 2:
+            raise ValueError("state must be a pair (F, H)")
+        _check_device_tensor(state[0], "state F", _fluid_dtype(precision), n)
+        _check_device_tensor(state[1], "state H", torch.float64, n)
+    if trace is not None:
+        if trace.dim() != 2:
+            raise ValueError("trace must be a 2-d tensor [rounds, n]")
+        _check_device_tensor(trace, "trace", torch.uint8, trace.shape[0] * n)
+    if out is not None:
+        if host:
+            _check_host_array(out, "out", n)
+        else:
+            _check_device_tensor(out, "out", torch.float64, n)
     if host:
         x = out if out is not None else np.empty(n, dtype=np.float64)
         vd = _host_vec(v, n)
@@ -296,7 +346,6 @@ def solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp32", normalize=Tr
         o.state_f = state[0].data_ptr()
         o.state_h = state[1].data_ptr()
     if trace is not None:
-        assert trace.dtype == torch.uint8 and trace.is_cuda and trace.shape[-1] == n
         o.flags |= TRACE
         o.trace_sets = trace.data_ptr()
         o.trace_rounds = trace.shape[0]
@@ -315,6 +364,13 @@ def power_solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp64", normal
     """Power-iteration comparator (pull SpMV) on the device; host as in solve."""
     torch = _torch()
     n = graph.n
+    if precision not in PRECISION:
+        raise ValueError("unknown precision %r" % (precision,))
+    if out is not None:
+        if host:
+            _check_host_array(out, "out", n)
+        else:
+            _check_device_tensor(out, "out", torch.float64, n)
     if host:
         x = out if out is not None else np.empty(n, dtype=np.float64)
         vd = _host_vec(v, n)
@@ -336,8 +392,11 @@ def diffuse_round(graph: Graph, F, H, theta: float, d=0.85, stream=None):
     """One threshold round in place on device tensors F (float32 or float64)
     and H (float64).  Returns (taken_nodes, taken_edges)."""
     torch = _torch()
+    if not isinstance(F, torch.Tensor) or F.dtype not in (torch.float32, torch.float64):
+        raise ValueError("F must be a float32 or float64 torch tensor")
     prec = FP64 if F.dtype == torch.float64 else FP32_FLUID
-    assert H.dtype == torch.float64 and F.is_cuda and H.is_cuda
+    _check_device_tensor(F, "F", F.dtype, graph.n)
+    _check_device_tensor(H, "H", torch.float64, graph.n)
     tn, te = ctypes.c_int64(), ctypes.c_int64()
     _check(_lib.di_diffuse_round(graph.handle, prec, float(d), float(theta), _ptr(F), _ptr(H),
                                  ctypes.byref(tn), ctypes.byref(te), _stream(stream)))
@@ -356,6 +415,13 @@ def solve_batch(graph: Graph, seed_ptr, seeds, seed_w=None, d=0.85, tol=1e-6, pr
     seeds = np.ascontiguousarray(seeds, dtype=np.int32)
     sw = None if seed_w is None else np.ascontiguousarray(seed_w, dtype=np.float64)
     B = len(seed_ptr) - 1
+    if precision not in PRECISION:
+        raise ValueError("unknown precision %r" % (precision,))
+    if out is not None:
+        if host:
+            _check_host_array(out, "out", B * graph.n)
+        else:
+            _check_device_tensor(out, "out", torch.float64, B * graph.n)
     if host:
         x = out if out is not None else np.empty((B, graph.n), dtype=np.float64)
     else:
@@ -394,7 +460,13 @@ def inject_update(old: Graph, new: Graph, F, H, d=0.85, stream=None):
     """di_inject_update: F += d (P_new - P_old) H on torch cuda tensors (F
     float32 or float64, H float64), in place."""
     torch = _torch()
+    if old.n != new.n:
+        raise ValueError("the two graphs must have the same number of nodes")
+    if not isinstance(F, torch.Tensor) or F.dtype not in (torch.float32, torch.float64):
+        raise ValueError("F must be a float32 or float64 torch tensor")
     prec = "fp64" if F.dtype == torch.float64 else "fp32"
+    _check_device_tensor(F, "F", F.dtype, new.n)
+    _check_device_tensor(H, "H", torch.float64, new.n)
     _check(_lib.di_inject_update(old.handle, new.handle, PRECISION[prec], float(d), _ptr(F),
                                  _ptr(H), _stream(stream)))
 

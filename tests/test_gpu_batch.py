@@ -183,6 +183,27 @@ def test_batch_topk_pads_short_vectors(di):
     np.testing.assert_allclose(vals[1, :11], xs[ids[1, :11]], rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_topk_with_many_ties(di, prec):
+    """An out-star whose hub has the highest id and 12,000 dangling leaves,
+    seeded at the hub: the leaves tie exactly (x_l = d/(k(1+d))), more than
+    the device keeps per vector in one pass.  The hub (x_c = 1/(1+d)) must come
+    first, then the lowest leaf ids; a second vector seeded at leaf 5 keeps all
+    its fluid there."""
+    k = 12000
+    g = wl.from_edges(k + 1, [k] * k, list(range(k)))
+    G = di.Graph(g)
+    ptr = np.array([0, 1, 2], np.int64)
+    seeds = np.array([k, 5], np.int32)
+    tol = 1e-12 if prec == "fp64" else 1e-7
+    ids, vals, _ = di.solve_batch_topk(G, ptr, seeds, k=100, d=D, tol=tol, precision=prec)
+    assert ids[0, 0] == k
+    assert abs(vals[0, 0] - 1.0 / (1.0 + D)) < (1e-12 if prec == "fp64" else 1e-6)
+    assert ids[0, 1:].tolist() == list(range(99))
+    np.testing.assert_allclose(vals[0, 1:], D / (k * (1.0 + D)), rtol=1e-6)
+    assert ids[1, 0] == 5 and abs(vals[1, 0] - 1.0) < 1e-15 and np.all(ids[1, 1:] == -1)
+
+
 @pytest.mark.parametrize("k", [0, 1025])
 def test_batch_topk_rejects_bad_k(di, c1, k):
     G = di.Graph(c1)

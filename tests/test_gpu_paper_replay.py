@@ -1,4 +1,4 @@
-"""The paper's six simulation scenarios (Section 5) on the GPU: the threshold
+"""The paper's six simulation scenarios (Section 4.1) on the GPU: the threshold
 D-iteration matches the exact limit within its bound and diffuses fewer links
 than the GPU power iteration uses (L per product) at the same stop rule --
 the paper's qualitative result, on the kernels of this library."""

@@ -51,3 +51,59 @@ def test_replay_of_recorded_sets(di, gname, prec, tol, sched):
     assert np.abs(Fg - Fo).sum() <= eps
     # the recorded sets follow the rule: a taken node held fluid when taken
     assert sets.sum() == st["nodes_diffused"]
+
+
+def _score(sched, F, outdeg, indeg):
+    """The selection scores of Section 4.3 (ALGO-OP: F_i/((#in_i+1)(#out_i+1)),
+    ALGO-OP2: F_i/(#out_i+1)) and of the plain threshold variant (F_i), written
+    out here from the paper, independent of the library and of the oracle."""
+    a = np.abs(F)
+    if sched == "op":
+        return a / ((indeg + 1.0) * (outdeg + 1.0))
+    if sched == "op2":
+        return a / (outdeg + 1.0)
+    return a
+
+
+@pytest.mark.parametrize("gname,sched,c", [
+    ("pagerank-10k", "op", 1.0),
+    ("pagerank-10k", "op2", 1.0),
+    ("pagerank-10k", "op", 1.0 / 16),
+    ("pagerank-10k", "op2", 1.0 / 32),
+    ("pagerank-10k", "mean", 0.25),
+    ("rand", "op", 1.0),
+    ("rand", "op2", 0.5),
+])
+def test_every_round_takes_the_top_of_its_score(di, gname, sched, c):
+    """Every round of a traced fp64 solve takes an upper set of the schedule's
+    score: on the oracle's replay of the recorded sets, each round's lowest
+    taken score is at least the highest score of the nodes it left holding
+    fluid.  A slip in the device's OP / OP2 weights (a sum for OP's product,
+    #in for OP2's #out) breaks this on graphs whose degrees vary."""
+    import torch
+    g = wl.recipe(gname) if gname != "rand" else wl.random_small(5000, 40000, seed=43, p_dangling=0.2)
+    G = di.Graph(g)
+    outdeg = g.outdeg.astype(np.float64)
+    indeg = np.bincount(g.col_idx, minlength=g.n).astype(np.float64)
+    F = torch.full((g.n,), (1 - D) / g.n, dtype=torch.float64, device="cuda")
+    H = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    F0 = F.cpu().numpy()
+    trace = torch.zeros((600, g.n), dtype=torch.uint8, device="cuda")
+    _, st = di.solve(G, d=D, tol=1e-10, precision="fp64", state=(F, H), trace=trace,
+                     tune=di.make_tune(sched, c))
+    rounds = st["rounds"]
+    assert 0 < rounds <= 600
+    sets = trace[:rounds].cpu().numpy().astype(bool)
+    Fo, Ho = F0, np.zeros(g.n)
+    checked = 0
+    for r in range(rounds):
+        S = sets[r]
+        assert np.all(Fo[S] != 0.0), r  # a taken node holds fluid
+        sc = _score(sched, Fo, outdeg, indeg)
+        left = (~S) & (Fo != 0.0)
+        if S.any() and left.any():
+            lo, hi = sc[S].min(), sc[left].max()
+            assert lo >= hi * (1.0 - 1e-9), (r, lo, hi)
+            checked += 1
+        Fo, Ho = oracle.apply_set(g, D, S, Fo, Ho)
+    assert checked >= rounds // 2

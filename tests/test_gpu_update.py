@@ -1,4 +1,4 @@
-"""GPU tests of the graph update (updating equation, Section 3.3): the fluid
+"""GPU tests of the graph update (updating equation, Section 3.2): the fluid
 injection F += d(P'-P)H against the oracle's, one round on signed fluid
 against the oracle's signed set step, and the full flow -- solve on P, change
 the graph, inject, resume on P' -- against the exact limit of P' (Theorem 4),

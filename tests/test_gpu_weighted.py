@@ -95,7 +95,7 @@ def test_weighted_server_matches_dense_limit(di, wg):
 
 
 def test_weighted_update_of_link_weights(di, wg):
-    """A change of the link weights of 5% of the rows, same links (Section 3.3
+    """A change of the link weights of 5% of the rows, same links (Section 3.2
     with P' from the new weights): the injected fluid against the oracle's
     F + d(P'-P)H on the dense weighted matrices, then the resumed solve
     against the dense weighted limit of P'."""

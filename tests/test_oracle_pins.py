@@ -132,7 +132,7 @@ def test_ppr_on_cycle(n):
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
 def test_renormalised_limit_is_completed_pagerank(seed):
-    """Section 3.4: H_inf / ||H_inf||_1 equals the PageRank of the matrix completed
+    """Section 3.3: H_inf / ||H_inf||_1 equals the PageRank of the matrix completed
     with V on its dangling columns (independent route: eigenvector of A)."""
     g = wl.random_small(40, 120, seed=seed, p_dangling=0.3)
     v = np.random.default_rng(seed).random(40)
@@ -157,7 +157,7 @@ def _partial(g, order, picks, v=None, d=D):
 @pytest.mark.parametrize("picks", [1, 7, 60, 400])
 def test_theorem1_invariant(order, picks):
     """Theorem 1: H_n + F_n = F_0 + d P H_n, componentwise, for any sequence.
-    Also: the running R of ALGO-REF with the dangling rule (Section 3.4) equals
+    Also: the running R of ALGO-REF with the dangling rule (Section 3.3) equals
     the remaining fluid ||F_n||_1."""
     g = wl.random_small(50, 160, seed=picks, p_dangling=0.25)
     r = _partial(g, order, picks)
@@ -182,7 +182,7 @@ def test_theorem2_equality_without_dangling(picks):
 
 @pytest.mark.parametrize("picks", [3, 40, 300])
 def test_theorem2_bounds_with_dangling(picks):
-    """With dangling nodes ||F||/(1-d) only bounds ||Y - H||_1 (Section 3.4), and
+    """With dangling nodes ||F||/(1-d) only bounds ||Y - H||_1 (Section 3.3), and
     Y - (H+F) = dP(I-dP)^{-1}F >= 0 is bounded by d||F||_1/(1-d)."""
     g = wl.random_small(45, 150, seed=picks, p_dangling=0.3)
     Y, _ = oracle.dense_exact(g, D)
@@ -220,6 +220,41 @@ def test_lemma_contraction_for_argmax(order):
         assert np.all(ratio <= 1 - (1 - D) / g.n + 1e-12)
     else:
         assert np.all(ratio <= 1 + 1e-12)
+
+
+# Six nodes, worked by hand: out-links 0->{1,2,3}, 1->{0}, 2->{0,1}, 3 dangling,
+# 4->{0,1,2,3}, 5->{0}; so #out = (3,1,2,0,4,1) and #in = (4,3,2,2,0,0).
+# V = (.30,.20,.10,.08,.22,.10), F_0 = (1-d)V.  Scores of F_0 / (1-d):
+#   MAX  F_i:                          .30 .20 .10 .08 .22 .10 -> node 0
+#   OP2  F_i/(#out_i+1):               .075 .10 .033 .08 .044 .05 -> node 1
+#   OP   F_i/((#in_i+1)(#out_i+1)):    .015 .025 .011 .027 .044 .05 -> node 5
+# Second picks (d = .85), after the first node's d*F is pushed to its children:
+#   MAX: node 0 sends .045 -> +.01275 to 1,2,3; F = (0,.04275,.02775,.02475,.033,.015) -> 1
+#   OP2: node 1 sends .03 -> +.0255 to 0; scores (.017625,-,.005,.012,.0066,.0075) -> 0
+#   OP:  node 5 sends .015 -> +.01275 to 0; scores (.0028875,.00375,.00167,.004,.0066,-) -> 4
+# A slip in either score (a sum for OP's product, #in for OP2's #out, a
+# dropped +1) moves the first pick to node 4 or 3.
+_SCORE_G = ([0, 0, 0, 1, 2, 2, 4, 4, 4, 4, 5], [1, 2, 3, 0, 0, 1, 0, 1, 2, 3, 0])
+_SCORE_V = np.array([0.30, 0.20, 0.10, 0.08, 0.22, 0.10])
+
+
+@pytest.mark.parametrize("order,first,second,h2", [
+    ("max", 0, 1, 0.15 * 0.20 + D * 0.15 * 0.30 / 3),
+    ("op2", 1, 0, 0.15 * 0.30 + D * 0.15 * 0.20),
+    ("op", 5, 4, 0.15 * 0.22),
+])
+def test_argmax_scores_by_hand(order, first, second, h2):
+    """Section 4.3: ALGO-OP takes argmax F_i/((#in_i+1)(#out_i+1)), ALGO-OP2
+    argmax F_i/(#out_i+1), ALGO-MAX argmax F_i (Section 4).  The first two picks
+    of the oracle on the hand-worked graph above, and the fluid each moved."""
+    g = wl.from_edges(6, *_SCORE_G)
+    np.testing.assert_array_equal(g.outdeg, [3, 1, 2, 0, 4, 1])
+    one = oracle.diter(g, D, 1e-300, order=order, v=_SCORE_V, max_picks=1)
+    assert np.flatnonzero(one["H"]).tolist() == [first]
+    assert one["H"][first] == pytest.approx((1 - D) * _SCORE_V[first], rel=1e-15)
+    two = oracle.diter(g, D, 1e-300, order=order, v=_SCORE_V, max_picks=2)
+    assert sorted(np.flatnonzero(two["H"]).tolist()) == sorted([first, second])
+    assert two["H"][second] == pytest.approx(h2, rel=1e-14)
 
 
 def test_jacobi_sets_equal_power_series():
@@ -349,7 +384,7 @@ def test_threshold_variant_uses_fewer_elementary_steps():
     assert s["stats"]["edges"] < p["stats"]["edges"]
 
 
-# ------------------------------------------------- graph updates (Section 3.3)
+# ------------------------------------------------- graph updates (Section 3.2)
 
 def _update_pair(seed):
     g0 = wl.random_small(40, 160, seed=seed, p_dangling=0.15)

@@ -1,5 +1,5 @@
 """Replay of the paper's simulation experiments on the CPU oracle: its graph
-generator at the six scenarios of Section 5 (checked against the dangling
+generator at the six scenarios of Section 4.1 (checked against the dangling
 counts its tables print), and its qualitative result -- every D-iteration
 order (PER, RAND, MAX, the threshold sweep, OP) reaches the target error with
 fewer elementary steps (out-links used) than MAT-ITER (L per product).  The

@@ -225,7 +225,7 @@ PAPER_SCENARIOS = {
 
 
 def paper_scenario(name: str, seed: int = 1) -> Graph:
-    """The paper's simulation graphs (simulation scenario of Section 5): the
+    """The paper's simulation graphs (simulation scenario of Section 4.1): the
     source and the destination of each link are drawn independently, node k
     with probability proportional to 1/k^alpha, each of the two laws carried
     to the nodes by N random transpositions of the rank order (so node order
