@@ -181,6 +181,31 @@ di_status di_power_solve(const di_graph* g, const double* v, const di_opts* opts
                          di_stats* stats, void* stream);
 
 /*
+ * di_power_solve without any allocation, for callers that cannot allocate
+ * device or pinned host memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arithmetic, kernels, results,
+ * statistics and errors as di_power_solve, with these differences:
+ *  - Its two iterates, per-link values and control block live in a fixed
+ *    scratch array of DI_NOALLOC_SCRATCH_BYTES in device memory, one per GPU,
+ *    held from the library's load until the process ends.  A graph of n
+ *    nodes needs 32 n bytes (DI_FP64) or 24 n bytes (DI_FP32_FLUID) of it,
+ *    plus 6.4 KB: larger graphs give DI_EINVAL (n above about 1.048e6 in
+ *    fp64, 1.398e6 in fp32).
+ *  - v and x must be device pointers: DI_DEVICE_PTRS is required (DI_EINVAL
+ *    otherwise).  DI_TIMING is rejected; stats.seconds is host time.
+ *  - The current device must be the graph's device.
+ *  - Every call on one GPU shares that GPU's scratch and leaves its contents
+ *    behind (the call initialises everything it reads): calls that overlap on
+ *    one GPU, from several host threads or streams, race and must be
+ *    serialised by the caller.
+ *  - It calls no hipMalloc, hipHostMalloc, hipFree or other allocating routine
+ *    (the control block's host copy is on the calling thread's stack).
+ */
+#define DI_NOALLOC_SCRATCH_BYTES (32u << 20)
+di_status di_power_solve_noalloc(const di_graph* g, const double* v, const di_opts* opts,
+                                 double* x, di_stats* stats, void* stream);
+
+/*
  * One threshold round on caller-provided device state (the kernel step of a
  * di_solve round): every node with F_i != 0 and |F_i| >= theta (compared in
  * fp64) is taken -- H_i += F_i, F_i = 0 -- and its fluid is pushed,

@@ -14,8 +14,11 @@
 //   F_0 = (1-d)V, F_{n+1} = d P F_n (fp32 gather), X_{n+1} = X_n + F_{n+1} (fp64),
 // whose increments are the Jacobi fluid of the D-iteration.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
 
 #include <hip/hip_ext.h>
 
@@ -219,35 +222,34 @@ struct PowWorkspace {
   PinnedBuf hctl;
 };
 
+// Device buffers of one power solve: the two iterates, the two per-link
+// values, the control block; and a host copy of the control block.
+struct PowBufs {
+  double* x0;
+  double* x1;
+  void* xs0;
+  void* xs1;
+  PowCtl* ctl;
+  PowCtl* hctl;
+};
+
+// Bytes a power solve of n nodes needs from its buffers (gathered type G).
 template <typename G>
-static di_status power_impl(Graph* g, const double* v, const di_opts* o, double* x,
-                            di_stats* st, hipStream_t s) {
-  const bool dev = (o->flags & DI_DEVICE_PTRS) != 0;
+static int64_t pow_bytes(int64_t n) {
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  return 2 * up(n * 8) + 2 * up(n * (int64_t)sizeof(G)) + up((int64_t)sizeof(PowCtl));
+}
+
+// The product loop and the flush on the given buffers.  vdev: device V or
+// NULL (uniform); out: device x or NULL.  timed: the solve's own time from
+// HIP events (else from the host clock around the stream's completion) and,
+// with DI_TIMING, per-launch events.
+template <typename G>
+static di_status power_run(Graph* g, const double* vdev, const di_opts* o, double* out,
+                           di_stats* st, hipStream_t s, const PowBufs& b, bool timed) {
   const bool delta = std::is_same<G, float>::value;
   const int64_t n = g->n;
   const int64_t max_iter = o->max_rounds > 0 ? o->max_rounds : 1000000;
-  if (v && !dev) validate_vector(v, n, "v");
-  PowWorkspace ws;
-  ws.x0.alloc(n * 8);
-  ws.x1.alloc(n * 8);
-  ws.xs0.alloc(n * sizeof(G));
-  ws.xs1.alloc(n * sizeof(G));
-  ws.ctl.alloc(sizeof(PowCtl));
-  ws.hctl.alloc(sizeof(PowCtl));
-  // a device v: checked with the residual partials of the control block,
-  // which k_pow_init clears afterwards
-  if (v && dev)
-    validate_device_vector(v, n, "v", &ws.ctl.as<PowCtl>()->acc[0][0],
-                           &ws.hctl.as<PowCtl>()->acc[0][0], s);
-  const double* vdev = nullptr;
-  if (v) {
-    if (dev) vdev = v;
-    else {
-      ws.v.alloc(n * 8);
-      DI_HIP(hipMemcpyAsync(ws.v.p, v, n * 8, hipMemcpyHostToDevice, s));
-      vdev = ws.v.as<double>();
-    }
-  }
   PowArgs<G> a;
   memset(&a, 0, sizeof(a));
   a.n = n;
@@ -260,18 +262,20 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
   a.d = o->d;
   a.tol = o->tol;
   a.max_iter = max_iter;
-  a.x[0] = ws.x0.as<double>();
-  a.x[1] = ws.x1.as<double>();
-  a.xs[0] = ws.xs0.as<G>();
-  a.xs[1] = ws.xs1.as<G>();
-  a.ctl = ws.ctl.as<PowCtl>();
+  a.x[0] = b.x0;
+  a.x[1] = b.x1;
+  a.xs[0] = static_cast<G*>(b.xs0);
+  a.xs[1] = static_cast<G*>(b.xs1);
+  a.ctl = b.ctl;
   a.delta = delta ? 1 : 0;
   const int grid_n = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 2048));
-  EventTimer timer(s);
+  std::unique_ptr<EventTimer> timer;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (timed) timer.reset(new EventTimer(s));
   k_pow_init<G><<<grid_n, kBlock, 0, s>>>(a);
   DI_HIP(hipGetLastError());
-  PowCtl* h = ws.hctl.as<PowCtl>();
-  LaunchTimer lt(s, (o->flags & DI_TIMING) != 0);
+  PowCtl* h = b.hctl;
+  LaunchTimer lt(s, timed && (o->flags & DI_TIMING) != 0);
   int k = 0;
   int chunk = 16;
   for (;;) {
@@ -292,7 +296,7 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
       }
       DI_HIP(hipGetLastError());
     }
-    DI_HIP(hipMemcpyAsync(h, ws.ctl.p, sizeof(PowCtl), hipMemcpyDeviceToHost, s));
+    DI_HIP(hipMemcpyAsync(h, b.ctl, sizeof(PowCtl), hipMemcpyDeviceToHost, s));
     DI_HIP(hipStreamSynchronize(s));
     if (h->done_at >= 0) break;
     // ||X_k - X_{k-1}||_1 decays by about d per product: plan the rest.
@@ -306,11 +310,6 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
   }
   const int K = h->done_at;  // X_K is the answer
   const double* xr = delta ? a.x[0] : a.x[K & 1];
-  double* out = dev ? x : nullptr;
-  if (x && !dev) {
-    ws.out.alloc(n * 8);
-    out = ws.out.as<double>();
-  }
   double* slots = &a.ctl->acc[0][0];
   k_pow_zero<<<1, kBlock, 0, s>>>(slots);
   DI_HIP(hipGetLastError());
@@ -318,13 +317,18 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
   DI_HIP(hipGetLastError());
   k_pow_sum_reduce<<<1, kBlock, 0, s>>>(slots, a.ctl);
   DI_HIP(hipGetLastError());
-  if (x) {
+  if (out) {
     k_pow_write<<<grid_n, kBlock, 0, s>>>(n, xr, a.ctl, o->normalize, out);
     DI_HIP(hipGetLastError());
   }
-  const double secs = timer.stop();
-  if (x && !dev) DI_HIP(hipMemcpyAsync(x, out, n * 8, hipMemcpyDeviceToHost, s));
-  DI_HIP(hipMemcpyAsync(h, ws.ctl.p, sizeof(PowCtl), hipMemcpyDeviceToHost, s));
+  double secs;
+  if (timer) {
+    secs = timer->stop();
+  } else {
+    DI_HIP(hipStreamSynchronize(s));
+    secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  DI_HIP(hipMemcpyAsync(h, b.ctl, sizeof(PowCtl), hipMemcpyDeviceToHost, s));
   DI_HIP(hipStreamSynchronize(s));
   if (st) {
     const double d = o->d, r = h->res, S = h->sum;
@@ -350,6 +354,106 @@ static di_status power_impl(Graph* g, const double* v, const di_opts* o, double*
   return DI_OK;
 }
 
+template <typename G>
+static di_status power_impl(Graph* g, const double* v, const di_opts* o, double* x,
+                            di_stats* st, hipStream_t s) {
+  const bool dev = (o->flags & DI_DEVICE_PTRS) != 0;
+  const int64_t n = g->n;
+  if (v && !dev) validate_vector(v, n, "v");
+  PowWorkspace ws;
+  ws.x0.alloc(n * 8);
+  ws.x1.alloc(n * 8);
+  ws.xs0.alloc(n * sizeof(G));
+  ws.xs1.alloc(n * sizeof(G));
+  ws.ctl.alloc(sizeof(PowCtl));
+  ws.hctl.alloc(sizeof(PowCtl));
+  // a device v: checked with the residual partials of the control block,
+  // which k_pow_init clears afterwards
+  if (v && dev)
+    validate_device_vector(v, n, "v", &ws.ctl.as<PowCtl>()->acc[0][0],
+                           &ws.hctl.as<PowCtl>()->acc[0][0], s);
+  const double* vdev = nullptr;
+  if (v) {
+    if (dev) vdev = v;
+    else {
+      ws.v.alloc(n * 8);
+      DI_HIP(hipMemcpyAsync(ws.v.p, v, n * 8, hipMemcpyHostToDevice, s));
+      vdev = ws.v.as<double>();
+    }
+  }
+  double* out = dev ? x : nullptr;
+  if (x && !dev) {
+    ws.out.alloc(n * 8);
+    out = ws.out.as<double>();
+  }
+  const PowBufs b{ws.x0.as<double>(), ws.x1.as<double>(), ws.xs0.p, ws.xs1.p,
+                  ws.ctl.as<PowCtl>(), ws.hctl.as<PowCtl>()};
+  const di_status rc = power_run<G>(g, vdev, o, out, st, s, b, true);
+  if (x && !dev) {
+    DI_HIP(hipMemcpyAsync(x, out, n * 8, hipMemcpyDeviceToHost, s));
+    DI_HIP(hipStreamSynchronize(s));
+  }
+  return rc;
+}
+
+// ------------------------------------------------ allocation-free variant
+
+// Fixed scratch of di_power_solve_noalloc: each device that runs it holds one
+// copy for the life of the process.  Host code never passes this name to a
+// kernel or a copy (on the host it only stands for the symbol); it uses the
+// device address that hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char scratch[DI_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (looked up once
+// per device, with that device current).
+static unsigned char* scratch_ptr() {
+  int dev = 0;
+  DI_HIP(hipGetDevice(&dev));
+  DI_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    DI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    DI_REQUIRE(p != nullptr, "scratch symbol has no device address");
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<unsigned char*>(g_scratch_ptr[dev]);
+}
+
+template <typename G>
+static di_status power_noalloc_impl(Graph* g, const double* v, const di_opts* o, double* x,
+                                    di_stats* st, hipStream_t s) {
+  DI_REQUIRE((o->flags & DI_DEVICE_PTRS) != 0,
+             "di_power_solve_noalloc takes device vectors only (set DI_DEVICE_PTRS)");
+  DI_REQUIRE((o->flags & DI_TIMING) == 0, "di_power_solve_noalloc does not take DI_TIMING");
+  int dev = 0;
+  DI_HIP(hipGetDevice(&dev));
+  DI_REQUIRE(dev == g->device, "the graph lives on another device than the current one");
+  const int64_t n = g->n;
+  DI_REQUIRE(pow_bytes<G>(n) <= (int64_t)DI_NOALLOC_SCRATCH_BYTES,
+             "graph too large for the fixed scratch of di_power_solve_noalloc");
+  unsigned char* p = scratch_ptr();
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  PowBufs b;
+  b.x0 = reinterpret_cast<double*>(p);
+  p += up(n * 8);
+  b.x1 = reinterpret_cast<double*>(p);
+  p += up(n * 8);
+  b.xs0 = p;
+  p += up(n * (int64_t)sizeof(G));
+  b.xs1 = p;
+  p += up(n * (int64_t)sizeof(G));
+  b.ctl = reinterpret_cast<PowCtl*>(p);
+  PowCtl hctl;  // host copy of the control block: on this thread's stack
+  b.hctl = &hctl;
+  if (v) validate_device_vector(v, n, "v", &b.ctl->acc[0][0], &hctl.acc[0][0], s);
+  return power_run<G>(g, v, o, x, st, s, b, false);
+}
+
 }  // namespace di
 
 using namespace di;
@@ -364,6 +468,21 @@ extern "C" di_status di_power_solve(const di_graph* gc, const double* v, const d
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = opts->precision == DI_FP64 ? power_impl<double>(g, v, opts, x, stats, s)
                                     : power_impl<float>(g, v, opts, x, stats, s);
+  });
+  return g != DI_OK ? g : rc;
+}
+
+extern "C" di_status di_power_solve_noalloc(const di_graph* gc, const double* v,
+                                            const di_opts* opts, double* x, di_stats* stats,
+                                            void* stream) {
+  di_status rc = DI_OK;
+  di_status g = guarded([&] {
+    DI_REQUIRE(gc != nullptr, "graph is NULL");
+    validate_d_tol(opts);
+    Graph* g = const_cast<di_graph*>(gc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = opts->precision == DI_FP64 ? power_noalloc_impl<double>(g, v, opts, x, stats, s)
+                                    : power_noalloc_impl<float>(g, v, opts, x, stats, s);
   });
   return g != DI_OK ? g : rc;
 }

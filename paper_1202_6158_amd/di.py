@@ -115,6 +115,7 @@ _SIGS = {
     "di_window_layout": [ctypes.c_int64, ctypes.POINTER(Tune), _P, _P],
     "di_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_power_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
+    "di_power_solve_noalloc": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_diffuse_round": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P],
     "di_solve_batch": [_P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(Opts), _P, _P, _P],
     "di_solve_batch_topk": [_P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(Opts), ctypes.c_int32,
@@ -386,6 +387,28 @@ def power_solve(graph: Graph, v=None, d=0.85, tol=1e-8, precision="fp64", normal
     s = st.as_dict()
     s["status"] = rc
     return x, s
+
+
+def power_solve_noalloc(graph: Graph, out, v=None, d=0.85, tol=1e-8, precision="fp64",
+                        normalize=True, max_rounds=0, stream=None, allow_notconv=False):
+    """di_power_solve_noalloc: the power iteration on the library's fixed device
+    scratch (no allocation inside the call).  out (and v, if given) are torch
+    cuda tensors of n float64; returns (out, stats dict)."""
+    torch = _torch()
+    n = graph.n
+    if precision not in PRECISION:
+        raise ValueError("unknown precision %r" % (precision,))
+    _check_device_tensor(out, "out", torch.float64, n)
+    if v is not None:
+        _check_device_tensor(v, "v", torch.float64, n)
+    o = make_opts(d, tol, precision, normalize, max_rounds, None, DEVICE_PTRS)
+    st = Stats()
+    rc = _lib.di_power_solve_noalloc(graph.handle, _ptr(v), ctypes.byref(o), _ptr(out),
+                                     ctypes.byref(st), _stream(stream))
+    _check(rc, allow=(ENOTCONV,) if allow_notconv else ())
+    s = st.as_dict()
+    s["status"] = rc
+    return out, s
 
 
 def diffuse_round(graph: Graph, F, H, theta: float, d=0.85, stream=None):
