@@ -88,8 +88,29 @@ def measured_traffic(tune, path=TRAFFIC_FILE):
     return None
 
 
-def cpu_baseline(g, d, tol, budget_s):
-    """The oracle's sequential D-iteration (threshold sweeps) on the host."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, d, tol, budget_s, refs=()):
+    """The CPU leg: the oracle timed on the host, and the oracle's references.
+
+    - value: the oracle's sequential D-iteration (threshold sweeps, fp64, one
+      thread) on the benchmark graph, full solves to ||F||_1 < tol.
+    - mat_iter_openmp: the oracle's MAT-ITER on every host core to the same
+      stop rule, on the same graph.
+    - references: for each (name, graph, d, ref_tol, v) in refs, the oracle's
+      limit (MAT-ITER on every core until ||X_n - X_n-1||_1 < ref_tol, or a
+      sparse direct solve up to 2e4 nodes), normalised; returned apart (as
+      numpy vectors) for the L1 errors of the GPU results.
+    Returns (summary dict, {name: x_ref})."""
     import oracle
     oracle.build(force=False)
     runs, t0 = 0, time.perf_counter()
@@ -99,11 +120,35 @@ def cpu_baseline(g, d, tol, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or runs >= 100:
             break
-    return {"value": runs / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full solve(s) of the benchmark graph to ||F||_1 < %g by the oracle's "
-                      "sequential threshold-sweep D-iteration (fp64, one thread), %.1f s" %
-                      (runs, tol, el),
-            "edges_per_s": r["stats"]["edges"] / (el / runs)}
+    out = {"value": runs / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": "%d full solve(s) of the benchmark graph to ||F||_1 < %g by the oracle's "
+                     "sequential threshold-sweep D-iteration (fp64, one thread), %.1f s" %
+                     (runs, tol, el),
+           "edges_per_s": r["stats"]["edges"] / (el / runs),
+           "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()}}
+    t0 = time.perf_counter()
+    p = oracle.power_omp(g, d, tol)
+    tp = time.perf_counter() - t0
+    out["mat_iter_openmp"] = {"solves_per_s": 1.0 / tp, "seconds": tp, "cores": p["threads"],
+                              "products": p["stats"]["rounds"],
+                              "note": "the oracle's MAT-ITER (fp64 pull, OpenMP over rows) to "
+                                      "||X_n - X_n-1||_1 < %g on every host core" % tol}
+    ref_x, ref_info = {}, {}
+    for name, rg, rd, rtol, rv in refs:
+        t0 = time.perf_counter()
+        if rg.n <= 20000:
+            ref_x[name] = oracle.sparse_exact(rg, rd, v=rv)[1]
+            how = "sparse direct solve of (I - dP) Y = (1-d) V"
+        else:
+            q = oracle.power_omp(rg, rd, rtol, v=rv)
+            ref_x[name] = q["x"]
+            how = ("MAT-ITER on %d cores to ||X_n - X_n-1||_1 < %g (%d products; its own L1 "
+                   "bound %.1e)" % (q["threads"], rtol, q["stats"]["rounds"],
+                                    2 * rd * q["stats"]["residual"] / (1 - rd)))
+        ref_info[name] = {"how": how, "seconds": time.perf_counter() - t0}
+        log("oracle reference %s: %.1f s" % (name, ref_info[name]["seconds"]))
+    out["references"] = ref_info
+    return out, ref_x
 
 
 COPY_MIB = 1024
@@ -352,6 +397,107 @@ def bench_paper_replay(di, args):
     return rows
 
 
+def _time_solves(fn, reps):
+    """Median wall time of reps calls of fn (each synchronised), and the last
+    call's result."""
+    import numpy as np
+    import torch
+    ts, r = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), r
+
+
+def bench_c1(di, args):
+    """The small graph: N = 10^4, mean degree 8, 10% dangling, fp64 fluid,
+    ||F||_1 < 1e-10, against the fp64 power iteration to the same stop.
+    Returns (summary, {result name: host x})."""
+    import workloads as wl
+    g = wl.recipe("pagerank-10k")
+    G = di.Graph(g)
+    tol = 1e-10
+    tune = None
+    if not args.no_autotune:
+        tune, _ = di.autotune(G, "solve", d=0.85, tol=tol, precision="fp64")
+    for _ in range(3):  # warm-up
+        di.solve(G, d=0.85, tol=tol, precision="fp64", tune=tune)
+        di.power_solve(G, d=0.85, tol=tol, precision="fp64")
+    t, (x, st) = _time_solves(lambda: di.solve(G, d=0.85, tol=tol, precision="fp64", tune=tune), 20)
+    tp, (xp, sp) = _time_solves(lambda: di.power_solve(G, d=0.85, tol=tol, precision="fp64"), 20)
+    out = {"workload": "pagerank-10k", "n": g.n, "links": g.m, "dangling": g.n_dangling,
+           "d": 0.85, "tol": tol, "precision": "fp64",
+           "tune": di.tune_dict(tune) if tune is not None else None,
+           "diter": {"ms_per_solve": 1e3 * t, "device_ms": 1e3 * st["seconds"],
+                     "rounds": st["rounds"], "edges_diffused": st["edges_diffused"],
+                     "edges_diffused_per_s": st["edges_diffused"] / t,
+                     "residual_l1": st["residual_l1"], "err_bound_l1": st["err_bound_l1"]},
+           "power": {"ms_per_solve": 1e3 * tp, "device_ms": 1e3 * sp["seconds"],
+                     "products": sp["rounds"], "link_visits": sp["rounds"] * g.m,
+                     "residual_l1": sp["residual_l1"], "err_bound_l1": sp["err_bound_l1"]},
+           "speedup_of_diter": tp / t}
+    return out, {"c1_diter": x.cpu().numpy(), "c1_power": xp.cpu().numpy()}, g
+
+
+def bench_c3(di, args):
+    """The web-shaped graph: N = 2e7, ~3e8 links, host blocks of 1000 ids with
+    80% of the links inside, 15% dangling; fp32 fluid, ||F||_1 < 1e-8, for
+    d = 0.85 and 0.90, against the power iteration (both variants) to the same
+    stop.  Returns (summary, {result name: host x}, graph)."""
+    import workloads as wl
+    log("generating web-20m")
+    t0 = time.perf_counter()
+    g = wl.recipe("web-20m")
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    G = di.Graph(g)
+    import torch
+    torch.cuda.synchronize()
+    res_s = time.perf_counter() - t0
+    log("web-20m n=%d links=%d (generated in %.1f s, resident in %.1f s)" % (g.n, g.m, gen_s, res_s))
+    tol, out, xs = 1e-8, {}, {}
+    for d in (0.85, 0.90):
+        tune = None
+        if not args.no_autotune:
+            tune, _ = di.autotune(G, "solve", d=d, tol=tol, precision="fp32")
+        di.solve(G, d=d, tol=tol, precision="fp32", tune=tune)
+        t, (x, st) = _time_solves(lambda: di.solve(G, d=d, tol=tol, precision="fp32", tune=tune), 3)
+        _, (_, stt) = _time_solves(lambda: di.solve(G, d=d, tol=tol, precision="fp32", tune=tune,
+                                                    timing=True), 1)
+        comp = {}
+        for prec in ("fp32", "fp64"):
+            di.power_solve(G, d=d, tol=tol, precision=prec)
+            tp, (xp, sp) = _time_solves(lambda: di.power_solve(G, d=d, tol=tol, precision=prec,
+                                                               timing=True), 2)
+            comp[prec] = {"ms_per_solve": 1e3 * tp, "products": sp["rounds"],
+                          "kernel_us_per_product": 1e6 * sp["kernel_seconds"] /
+                          max(1, sp["kernel_launches"]),
+                          "residual_l1": sp["residual_l1"]}
+            xs["c3_d%.2f_power_%s" % (d, prec)] = xp.cpu().numpy()
+            del xp
+        best = min(comp, key=lambda k: comp[k]["ms_per_solve"])
+        key = "d=%.2f" % d
+        out[key] = {"tune": di.tune_dict(tune) if tune is not None else None,
+                    "diter": {"ms_per_solve": 1e3 * t, "rounds": st["rounds"],
+                              "edges_diffused": st["edges_diffused"],
+                              "edges_diffused_per_s": st["edges_diffused"] / t,
+                              "round_kernel_us": 1e6 * stt["kernel_seconds"] /
+                              max(1, stt["kernel_launches"]),
+                              "residual_l1": st["residual_l1"],
+                              "err_bound_l1": st["err_bound_l1"]},
+                    "power": comp, "best_power_variant": best,
+                    "speedup_of_diter": comp[best]["ms_per_solve"] / (1e3 * t)}
+        xs["c3_d%.2f_diter" % d] = x.cpu().numpy()
+        del x
+    del G
+    return ({"workload": "web-20m", "n": g.n, "links": g.m, "dangling": g.n_dangling,
+             "tol": tol, "precision": "fp32 fluid, fp64 history", "generate_s": gen_s,
+             "residency_s": res_s, "by_d": out}, xs, g)
+
+
 SERVE_GRAPHS = ("serve-100k", "serve-500k", "serve-1m", "serve-5m")
 SERVE_TOLS = (1e-4, 1e-6, 1e-8)
 
@@ -519,9 +665,11 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-update", action="store_true")
     ap.add_argument("--no-replay", action="store_true")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 10^4-node fp64 solve")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 2e7-node web-shaped graph")
     ap.add_argument("--no-autotune", action="store_true",
                     help="library default knobs instead of di_autotune's choice")
-    ap.add_argument("--section", choices=["ppr", "serve", "update", "replay"],
+    ap.add_argument("--section", choices=["ppr", "serve", "update", "replay", "c1", "c3"],
                     help="run only this part and print its JSON (profiling runs)")
     ap.add_argument("--tune", metavar="SCHED:C:WLOG:THREADS",
                     help="fixed knobs for the single solve instead of autotuning (profiling runs)")
@@ -573,7 +721,9 @@ def main():
                 "update": lambda: bench_update(di, G, g, args, None if args.no_autotune else
                                                di.autotune(G, "solve", d=args.d, tol=args.tol,
                                                            precision=args.precision)[0]),
-                "replay": lambda: bench_paper_replay(di, args)}[args.section]()
+                "replay": lambda: bench_paper_replay(di, args),
+                "c1": lambda: bench_c1(di, args)[0],
+                "c3": lambda: bench_c3(di, args)[0]}[args.section]()
         print(json.dumps({"section": args.section, "result": part}), flush=True)
         return
 
@@ -633,6 +783,7 @@ def main():
                       "residual_l1": ps["residual_l1"], "x": pouts[-1][0]}
     best = min(comp, key=lambda k: comp[k]["ms_per_solve"])
     l1_di_vs_power = float(torch.sum(torch.abs(x_di - comp["fp64"]["x"])).item())
+    x_pow64 = comp["fp64"]["x"].cpu().numpy()
     for k in comp:
         comp[k].pop("x")
     log("power: fp64 %.3f ms, fp32 %.3f ms" % (comp["fp64"]["ms_per_solve"], comp["fp32"]["ms_per_solve"]))
@@ -677,6 +828,15 @@ def main():
                      "timing": "hipExtLaunchKernel begin/end events on the solve's stream, "
                                "%d launches over %d solves" % (kl, len(stats))},
     }
+    # results whose L1 error against the oracle is reported (host copies)
+    results = {"c2_diter": x_di.cpu().numpy(), "c2_power_fp64": x_pow64}
+    refs = [("c2", g, args.d, 1e-13, None)]
+    if not args.no_c1:
+        out["c1"], xs1, g1 = bench_c1(di, args)
+        results.update(xs1)
+        refs.append(("c1", g1, 0.85, 0.0, None))
+        log("c1: diter %.3f ms, power %.3f ms" % (out["c1"]["diter"]["ms_per_solve"],
+                                                  out["c1"]["power"]["ms_per_solve"]))
     if not args.no_ppr:
         out["ppr_batch"] = bench_ppr_batch(di, G, g, args)
     if not args.no_update:
@@ -685,11 +845,40 @@ def main():
         out["paper_replay"] = bench_paper_replay(di, args)
     if not args.no_serve:
         out["serve"] = bench_serve(di, args)
+    if not args.no_c3:
+        del G
+        torch.cuda.empty_cache()
+        out["c3"], xs3, g3 = bench_c3(di, args)
+        results.update(xs3)
+        for d3 in (0.85, 0.90):
+            refs.append(("c3_d%.2f" % d3, g3, d3, 1e-10, None))
+        for k, v in out["c3"]["by_d"].items():
+            log("c3 %s: diter %.1f ms, power %.1f ms" % (k, v["diter"]["ms_per_solve"],
+                                                        v["power"][v["best_power_variant"]]
+                                                        ["ms_per_solve"]))
     if args.copy_calibration:
         out["copy_calibration_bytes"] = copy_calibration()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(g, args.d, args.tol, args.cpu_seconds)
+        out["cpu_baseline"], ref_x = cpu_baseline(g, args.d, args.tol, args.cpu_seconds, refs)
+        # L1 error of every reported result against the oracle's fp64 limit
+        l1 = {}
+        for name, x in results.items():
+            ref = next(ref_x[r] for r in sorted(ref_x, key=len, reverse=True)
+                       if name.startswith(r + "_"))
+            l1[name] = float(np.abs(x - ref).sum())
+        out["l1_vs_oracle"] = l1
+        out["comparator"]["l1_power_fp64_vs_oracle"] = l1["c2_power_fp64"]
+        out["l1_vs_oracle_headline"] = l1["c2_diter"]
+        if "c1" in out:
+            out["c1"]["diter"]["l1_vs_oracle"] = l1["c1_diter"]
+            out["c1"]["power"]["l1_vs_oracle"] = l1["c1_power"]
+        if "c3" in out:
+            for d3 in (0.85, 0.90):
+                e = out["c3"]["by_d"]["d=%.2f" % d3]
+                e["diter"]["l1_vs_oracle"] = l1["c3_d%.2f_diter" % d3]
+                for prec in ("fp32", "fp64"):
+                    e["power"][prec]["l1_vs_oracle"] = l1["c3_d%.2f_power_%s" % (d3, prec)]
     print(json.dumps(out), flush=True)
 
 

@@ -110,3 +110,25 @@ def test_summarize_trace_separates_launches_after_the_stop(bench, tmp_path, caps
     line = capsys.readouterr().out.strip()
     assert "calls     3" in line and "working     2" in line
     assert "avg_working_us     45.00" in line and "returned-at-once 1" in line
+
+
+def test_cpu_leg_times_the_oracle_and_returns_its_references(bench):
+    """The CPU leg on a small graph: the sequential and OpenMP baselines are
+    reported with their core counts, and each reference is the oracle's exact
+    limit (direct solve for small graphs, MAT-ITER on every core otherwise)."""
+    import numpy as np
+    import oracle
+    import workloads as wl
+    g = wl.random_small(300, 1500, seed=3)
+    big = wl.recipe("pagerank-10k", n=30000, seed=9)
+    out, refs = bench.cpu_baseline(g, 0.85, 1e-8, 0.05,
+                                   refs=[("small", g, 0.85, 0.0, None),
+                                         ("big", big, 0.9, 1e-12, None)])
+    assert out["cores"] == 1 and out["value"] > 0
+    assert out["mat_iter_openmp"]["cores"] >= 1 and out["mat_iter_openmp"]["products"] > 0
+    assert out["host"]["nproc"] >= 1
+    assert set(refs) == {"small", "big"}
+    assert np.abs(refs["small"] - oracle.dense_exact(g, 0.85)[1]).sum() < 1e-12
+    # the sequential MAT-ITER (exact up to its own stop) on the larger graph
+    seq = oracle.power(big, 0.9, 1e-13)["x"]
+    assert np.abs(refs["big"] - seq).sum() < 2 * 0.9 * 1e-12 / 0.1 + 1e-12

@@ -115,9 +115,9 @@ def test_inject_rejects_mismatched_graphs(di):
 def test_update_at_one_million_nodes(di):
     """The benchmark's update at full size: 1% of the 10^6-node graph's rows get
     new out-links after an fp32 solve; inject + resume to 1e-8.  Theorem 1 for
-    P' on every node of the device state, and agreement with the power
-    iteration on P' within both bounds."""
-    import torch
+    P' on every node of the device state, and the result within its bound of
+    the oracle's limit of P' (MAT-ITER on every host core to
+    ||X_n - X_n-1||_1 < 1e-12, plus that stop's own bound)."""
     g0 = wl.recipe("powerlaw-1m")
     g1 = wl.modify_graph(g0, 0.01, seed=78)
     G0, G1 = di.Graph(g0), di.Graph(g1)
@@ -130,9 +130,10 @@ def test_update_at_one_million_nodes(di):
     src = np.repeat(np.arange(g1.n, dtype=np.int32), deg)
     PH = np.bincount(g1.col_idx, weights=Hn[src] / deg[src], minlength=g1.n)
     assert np.abs(Hn + Fn - ((1 - D) / g1.n + D * PH)).sum() < 1e-6
-    xp, sp = di.power_solve(G1, d=D, tol=1e-10, precision="fp64")
-    l1 = float(torch.sum(torch.abs(x - xp)).item())
-    assert l1 <= st["err_bound_l1"] + sp["err_bound_l1"] + 1e-6
+    ref = oracle.power_omp(g1, D, 1e-12)
+    ref_bound = 2 * D * ref["stats"]["residual"] / ((1 - D) * ref["X"].sum())
+    l1 = float(np.abs(x.cpu().numpy() - ref["x"]).sum())
+    assert l1 <= st["err_bound_l1"] + ref_bound + 1e-6
 
 
 @pytest.mark.parametrize("prec,tol,eps", [("fp64", 1e-11, 1e-12), ("fp32", 1e-8, 1e-6)])

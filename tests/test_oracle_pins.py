@@ -482,3 +482,22 @@ def test_weighted_set_steps_reach_the_weighted_limit():
         F, H, _ = oracle.set_step_weighted(g, w, D, nf / g.n, F, H)
     np.testing.assert_allclose((H + F) / (H + F).sum(), oracle.dense_exact_weighted(g, w, D)[1],
                                atol=1e-12)
+
+
+def test_openmp_mat_iter_is_the_sequential_mat_iter():
+    """The oracle's OpenMP MAT-ITER (pull over in-links, used for the CPU
+    baseline and the large references) takes the same products as the
+    sequential push MAT-ITER: same count, iterates equal to rounding, and the
+    exact limit at a tight stop -- also with repeated links, self-loops and a
+    personalisation vector."""
+    g = wl.random_small(500, 4000, seed=11)
+    v = np.random.default_rng(2).random(g.n)
+    v /= v.sum()
+    for vv in (None, v):
+        a = oracle.power(g, 0.85, 1e-12, v=vv)
+        b = oracle.power_omp(g, 0.85, 1e-12, v=vv)
+        assert a["stats"]["rounds"] == b["stats"]["rounds"]
+        assert np.abs(a["X"] - b["X"]).max() < 1e-15
+        assert b["threads"] >= 1
+    y = oracle.power_omp(g, 0.85, 1e-15, v=v)["x"]
+    assert np.abs(y - oracle.dense_exact(g, 0.85, v)[1]).sum() < 1e-13
