@@ -85,10 +85,19 @@ enum {
 };
 
 /* Tuning knobs (all optional; zero = library default). */
+/* di_tune.window_log2: the whole graph is one window, held in the LDS of one
+   workgroup that runs every round of a di_solve itself (rounds separated by
+   barriers, not launches); graphs of at most DI_SMALL_MAX_NODES nodes and
+   fewer than 2^31 links (DI_EINVAL otherwise).  di_autotune tries it for
+   such graphs.  Batches and servers take it as the default window. */
+#define DI_WINDOW_WHOLE (-1)
+#define DI_SMALL_MAX_NODES 16384
+
 typedef struct di_tune {
   int32_t schedule;    /* DI_SCHED_* */
   float c;             /* threshold factor (default 1.0) */
-  int32_t window_log2; /* destination window of the binned scatter: 2^k nodes (8..14) */
+  int32_t window_log2; /* destination window of the binned scatter: 2^k nodes (8..14), or
+                          DI_WINDOW_WHOLE */
   int32_t check_every; /* rounds between host checks of the device done flag (0 = adaptive) */
   int32_t threads;     /* round workgroup size: 512 (default, 0) or 1024 (more loads in flight) */
   int32_t tables;      /* per-window segment tables of the binned scatter: 0 = in LDS when they
@@ -147,9 +156,11 @@ di_status di_graph_destroy(di_graph* g); /* DI_EBUSY while a server references i
  * The binned scatter's layout that solves on a graph of n nodes get under
  * the given knobs (tune may be NULL = defaults): windows of 2^window_log2
  * nodes, with the per-window segment tables in LDS (*global_tables = 0) or
- * read from global memory (1).  Host only: touches no device.  DI_EINVAL if
- * no layout fits (n above 134,217,728 nodes, or tune->tables = 1 above
- * ~25M nodes) or if an output pointer is NULL.
+ * read from global memory (1); tune->window_log2 = DI_WINDOW_WHOLE gives
+ * DI_WINDOW_WHOLE (for n <= DI_SMALL_MAX_NODES).  Host only: touches no
+ * device.  DI_EINVAL if no layout fits (n above 134,217,728 nodes, or
+ * tune->tables = 1 above ~25M nodes, or DI_WINDOW_WHOLE above
+ * DI_SMALL_MAX_NODES) or if an output pointer is NULL.
  */
 di_status di_window_layout(int64_t n, const di_tune* tune, int32_t* window_log2,
                            int32_t* global_tables);
@@ -288,7 +299,9 @@ typedef struct di_tune_trial {
  * schedule x c in {1/32, 1/16, 1/8, 1/4, 1/2, 1, 2} at the default window,
  * then the best pair at larger and smaller windows, one size at a time in
  * each direction while the time improves, then the winner with 1024-thread
- * workgroups.  Any schedule converges to the same limit (the order
+ * workgroups; for DI_TUNE_SOLVE on a graph of at most DI_SMALL_MAX_NODES
+ * nodes, also every schedule x c in the whole-graph window (DI_WINDOW_WHOLE).
+ * Any schedule converges to the same limit (the order
  * independence of Sections 2.2 and 3.1), so only speed is compared.
  * The default knobs (mean, c = 1) run first; every other candidate gets at
  * most four times their rounds (at least 64, at most opts->max_rounds when

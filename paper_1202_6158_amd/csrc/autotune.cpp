@@ -134,6 +134,15 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
       const Trial t = run(win.tune.schedule, win.tune.c, win.tune.window_log2, 1024);
       if (better(t, win)) win = t;
     }
+    // 4. single solves on graphs that one workgroup's LDS holds: the
+    //    whole-graph window at every schedule x threshold factor
+    if (mode == DI_TUNE_SOLVE && g->n <= DI_SMALL_MAX_NODES && g->m < (1ll << 31)) {
+      for (int sc : scheds)
+        for (float c : cs) {
+          const Trial t = run(sc, c, DI_WINDOW_WHOLE);
+          if (better(t, win)) win = t;
+        }
+    }
     const int nt = (int)done.size();
     for (int k = 0; k < nt && k < max_trials; ++k) {
       trials[k].tune = done[k].tune;

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include <hip/hip_ext.h>
 
@@ -42,6 +43,7 @@ struct Workspace {
   DevBuf F, H, v, x, bstart, ctl, flacc, active;
   DevBuf pairs[2], cnt[2], slots;
   DevBuf soff, soffT, capT;  // nb x nb segment tables
+  DevBuf front;              // frontier list of the whole-graph window (k_small)
   PinnedBuf hctl, hctl2;     // host copies of the control blocks (two in flight while polling)
   hipEvent_t ev[2] = {nullptr, nullptr};  // completion of those copies
   Workspace() = default;
@@ -1050,6 +1052,294 @@ static void run_rounds(const DiArgs<T>& a, Workspace* ws, int sched, int check_e
   }
 }
 
+// ------------------------------------------------- whole graph in one window
+
+// Small graphs (n <= DI_SMALL_MAX_NODES): the whole fluid vector lives in the
+// LDS of one 1024-thread workgroup (fp64), which runs every round itself,
+// rounds separated by barriers instead of launches.  Round r: the fresh fp64
+// ||F_r||_1 (Theorem 2 stop), the mean and the largest score of the nodes
+// holding fluid; theta_r = c times that mean (never above the largest score,
+// so every round takes a node).  Every node reaching theta_r is taken
+// (H_i += F_i, F_i = 0) and, if it has out-links, listed in a frontier list in
+// global memory (first link, degree, share), all before any push; the list is
+// then pushed a chunk at a time through LDS staging, d F_i p(j,i) added into
+// the LDS fluid (each push rounded to the fluid type first, as a stored record
+// would be).  In fp32 the fluid is rounded to fp32 at the end of each round, as
+// a stored F would be.
+constexpr int kSmallThreads = 512;
+constexpr int kSmallP = 4;  // frontier entries per thread per chunk, at most
+
+struct FrontEntry {
+  int64_t row;   // first out-link
+  double share;  // d F_i / outdeg_i (weighted graphs: d F_i)
+  int32_t deg;
+  int32_t pad;
+};
+
+constexpr int kSmallRun = 8;  // consecutive links per thread per step of the push
+
+template <typename T, int SCHED>
+__global__ __launch_bounds__(kSmallThreads) void k_small(DiArgs<T> a, FrontEntry* __restrict__ front,
+                                                         int chunk, int cache_deg) {
+  constexpr int NT = kSmallThreads;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = (int)a.n;
+  double* f = reinterpret_cast<double*>(smem);                    // [n]
+  int64_t* s_brow = reinterpret_cast<int64_t*>(f + n);            // [chunk]
+  double* s_bsh = reinterpret_cast<double*>(s_brow + chunk);      // [chunk]
+  int32_t* s_beo = reinterpret_cast<int32_t*>(s_bsh + chunk);     // [chunk + 1]
+  int32_t* s_deg = s_beo + chunk + 1;                             // [n] when cache_deg
+  __shared__ double s_red[block_reduce_k_scratch<NT, 4>()];
+  __shared__ long long s_scr[2 * (NT / 64)];
+  const int tid = threadIdx.x;
+  const double d = a.d;
+  const int P = chunk / NT;  // entries per thread per chunk
+  if (cache_deg)
+    for (int q = tid; q < n; q += NT) s_deg[q] = a.deg[q];
+  auto degree = [&](int q) { return cache_deg ? s_deg[q] : a.deg[q]; };
+  auto score = [&](int q, double af) {
+    const int dg = SCHED != DI_SCHED_MEAN ? degree(q) : -1;
+    return node_score<SCHED>(af, dg, SCHED == DI_SCHED_OP ? a.indeg[q] : 0);
+  };
+  // sums of the current fluid: ||F||_1, score sum, nodes holding fluid; max score
+  double v[4], smax;
+  auto sums = [&] {
+    v[0] = v[1] = v[2] = v[3] = 0.0;
+    smax = 0.0;
+    for (int q = tid; q < n; q += NT) {
+      const double af = fabs(f[q]);
+      if (af > 0.0) {
+        const double sc = score(q, af);
+        v[0] += af;
+        v[1] += sc;
+        v[2] += 1.0;
+        smax = fmax(smax, sc);
+      } else if (f[q] != f[q]) {
+        v[0] = NAN;
+      }
+    }
+    block_reduce_k<NT, 4>(v, smax, s_red);
+  };
+  for (int q = tid; q < n; q += NT) f[q] = (double)a.F[q];
+  __syncthreads();
+  sums();
+  long long nodes_total = 0, edges_total = 0, last_taken = 0, last_edges = 0;
+  double theta = 0.0, nf = 0.0;
+  int reason = 0;
+  int64_t r = 0;
+  for (;; ++r) {
+    nf = v[0];
+    if (!isfinite(nf)) reason = 2;
+    else if (nf < a.tol) reason = 1;
+    else if (r >= a.max_rounds) reason = 3;
+    if (reason) break;  // uniform
+    theta = fmin(a.c * v[1] / v[2], smax);
+    // 1. take every node of S_r, all before any push: count this thread's
+    //    pushing nodes and their links, place them (block scan), then take
+    //    them and stage them -- straight into LDS when they fit one chunk,
+    //    else into the frontier list
+    long long mine = 0, mylinks = 0;
+    for (int q = tid; q < n; q += NT) {
+      const double af = fabs(f[q]);
+      if (af > 0.0 && score(q, af) >= theta) {
+        const int dg = degree(q);
+        if (dg > 0) {
+          ++mine;
+          mylinks += dg;
+        }
+      }
+    }
+    long long pos = 0, eoff = 0, total = 0, etotal = 0;
+    block_exscan2<NT>(mine, mylinks, s_scr, &pos, &eoff, &total, &etotal);
+    const bool direct = total <= chunk;  // uniform
+    double cnt[4] = {0.0, 0.0, 0.0, 0.0};  // taken, links
+#pragma unroll 4
+    for (int q = tid; q < n; q += NT) {
+      const int64_t row = a.row_ptr[q];  // not behind the test: loads of several nodes overlap
+      const double x = f[q], af = fabs(x);
+      if (!(af > 0.0) || !(score(q, af) >= theta)) continue;
+      const int dg = degree(q);
+      f[q] = 0.0;
+      unsafeAtomicAdd(&a.H[q], x);  // H_i += F_i (one writer per node; nothing waits on it)
+      if (a.trace && r < a.trace_rounds) a.trace[r * a.n + q] = 1;
+      cnt[0] += 1.0;
+      cnt[1] += dg;
+      if (dg > 0) {
+        const double sh = a.weighted ? d * x : d * x / (double)dg;
+        if (direct) {
+          s_beo[pos] = (int32_t)eoff;
+          s_brow[pos] = row;
+          s_bsh[pos] = sh;
+          eoff += dg;
+        } else {
+          FrontEntry e;
+          e.row = row;
+          e.share = sh;
+          e.deg = dg;
+          e.pad = 0;
+          front[pos] = e;
+        }
+        ++pos;
+      }
+    }
+    __syncthreads();  // the staging (or the list) and the zeroed fluid are complete
+    // 2. push the staged nodes [0, cn) with their links [0, links)
+    auto push = [&](int cn, long long links) {
+      for (long long t00 = (long long)tid * kSmallRun; t00 < links;
+           t00 += (long long)NT * kSmallRun) {
+        int kk = upper_idx(s_beo, cn, t00);
+        long long nxt = kk + 1 < cn ? s_beo[kk + 1] : links;
+        int64_t lb = s_brow[kk] - s_beo[kk];
+        double sh = s_bsh[kk];
+        int64_t ei[kSmallRun];
+        double pv[kSmallRun];
+#pragma unroll
+        for (int u = 0; u < kSmallRun; ++u) {
+          const long long t = t00 + u;
+          ei[u] = -1;
+          if (t < links) {
+            while (t >= nxt) {
+              ++kk;
+              nxt = kk + 1 < cn ? s_beo[kk + 1] : links;
+              lb = s_brow[kk] - s_beo[kk];
+              sh = s_bsh[kk];
+            }
+            ei[u] = lb + t;
+            pv[u] = sh;
+          }
+        }
+        int32_t dst[kSmallRun];
+#pragma unroll
+        for (int u = 0; u < kSmallRun; ++u)
+          if (ei[u] >= 0) {
+            dst[u] = a.col[ei[u]];
+            if (a.weighted) pv[u] *= a.w[ei[u]];
+          }
+#pragma unroll
+        for (int u = 0; u < kSmallRun; ++u)
+          if (ei[u] >= 0) atomicAdd(&f[dst[u]], (double)(T)pv[u]);
+      }
+      __syncthreads();
+    };
+    if (direct) {
+      if (total > 0) push((int)total, etotal);
+    } else {
+      // the list a chunk of P entries per thread at a time
+      for (long long c0 = 0; c0 < total; c0 += chunk) {
+        const int cn = (int)min((long long)chunk, total - c0);
+        FrontEntry e[kSmallP];
+        long long my_links = 0;
+#pragma unroll
+        for (int u = 0; u < kSmallP; ++u) {
+          const int k = tid * P + u;
+          e[u].deg = 0;
+          if (u < P && k < cn) {
+            e[u] = front[c0 + k];
+            my_links += e[u].deg;
+          }
+        }
+        long long lo = 0, links = 0;
+        lo = block_exscan<NT>(my_links, s_scr, &links);
+#pragma unroll
+        for (int u = 0; u < kSmallP; ++u) {
+          const int k = tid * P + u;
+          if (u < P && k < cn) {
+            s_beo[k] = (int32_t)lo;
+            s_brow[k] = e[u].row;
+            s_bsh[k] = e[u].share;
+            lo += e[u].deg;
+          }
+        }
+        __syncthreads();
+        push(cn, links);
+      }
+    }
+    // 3. the round's fluid as stored in the fluid type; the next round's sums
+    if (!std::is_same<T, double>::value) {
+      for (int q = tid; q < n; q += NT) f[q] = (double)(T)f[q];
+      __syncthreads();
+    }
+    double unused = 0.0;
+    block_reduce_k<NT, 4>(cnt, unused, s_red);
+    last_taken = (long long)cnt[0];
+    last_edges = (long long)cnt[1];
+    nodes_total += last_taken;
+    edges_total += last_edges;
+    sums();
+  }
+  for (int q = tid; q < n; q += NT) a.F[q] = (T)f[q];
+  if (tid == 0) {
+    Ctl* c = a.ctl;
+    c->stop_round = (int)r - 1;
+    c->reason = reason;
+    c->nf = nf;
+    c->theta = theta;
+    c->nodes_total = nodes_total;
+    c->edges_total = edges_total;
+    c->last_taken = last_taken;
+    c->last_edges = last_edges;
+  }
+}
+
+// LDS bytes of k_small for n nodes and a chunk of c frontier entries (plus
+// the degrees when they are cached).
+static size_t small_lds_bytes(int64_t n, int c, bool cache_deg = false) {
+  return (size_t)n * 8 + (size_t)c * 16 + (size_t)(c + 1) * 4 + (cache_deg ? (size_t)n * 4 : 0);
+}
+
+template <typename T>
+static void launch_small(const DiArgs<T>& a, Workspace* ws, int sched, hipStream_t s,
+                         LaunchTimer* lt) {
+  // the dynamic LDS limit of the kernel instances (set once): what the static
+  // part leaves of the workgroup's 160 KiB
+  static const size_t dyn_limit = [] {
+    size_t lim = ~(size_t)0;
+    auto one = [&](const void* k) {
+      hipFuncAttributes fa;
+      DI_HIP(hipFuncGetAttributes(&fa, k));
+      int dev = 0, mx = 0;
+      DI_HIP(hipGetDevice(&dev));
+      DI_HIP(hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      const size_t dl = (size_t)mx - fa.sharedSizeBytes;
+      DI_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl));
+      lim = std::min(lim, dl);
+    };
+    one((const void*)k_small<T, DI_SCHED_MEAN>);
+    one((const void*)k_small<T, DI_SCHED_OP2>);
+    one((const void*)k_small<T, DI_SCHED_OP>);
+    return lim;
+  }();
+  // largest chunk (a multiple of the block, at most kSmallP entries per thread)
+  int chunk = kSmallP * kSmallThreads;
+  while (chunk > kSmallThreads && small_lds_bytes(a.n, chunk) > dyn_limit) chunk -= kSmallThreads;
+  DI_REQUIRE(small_lds_bytes(a.n, chunk) <= dyn_limit, "graph too large for the whole-graph window");
+  // the degrees stay in LDS too when they fit beside a chunk of at least 1024
+  int cache_deg = 0;
+  for (int c = chunk; c >= std::min(chunk, 2 * kSmallThreads); c -= kSmallThreads)
+    if (small_lds_bytes(a.n, c, true) <= dyn_limit) {
+      chunk = c;
+      cache_deg = 1;
+      break;
+    }
+  const size_t smem = small_lds_bytes(a.n, chunk, cache_deg != 0);
+  ws->front.alloc((size_t)a.n * sizeof(FrontEntry));
+  FrontEntry* front = ws->front.as<FrontEntry>();
+  auto go = [&](auto kern) {
+    if (lt && lt->on) {
+      hipEvent_t e0, e1;
+      lt->next(&e0, &e1);
+      hipExtLaunchKernelGGL(kern, dim3(1), dim3(kSmallThreads), smem, s, e0, e1, 0, a, front,
+                            chunk, cache_deg);
+    } else {
+      kern<<<1, kSmallThreads, smem, s>>>(a, front, chunk, cache_deg);
+    }
+    DI_HIP(hipGetLastError());
+  };
+  if (sched == DI_SCHED_OP2) go(k_small<T, DI_SCHED_OP2>);
+  else if (sched == DI_SCHED_OP) go(k_small<T, DI_SCHED_OP>);
+  else go(k_small<T, DI_SCHED_MEAN>);
+}
+
 // Zero the flush slots of the vectors of this launch (slot vmap[blockIdx.x]).
 template <typename T>
 __global__ void k_zero_flush(DiArgs<T> a) {
@@ -1106,6 +1396,7 @@ static di_status status_of(const Ctl& h) {
 struct TuneParams {
   int sched, wlog, check_every, threads;
   bool gt;
+  bool whole;  // single solves: the whole graph in one workgroup's LDS (k_small)
   double c;
 };
 
@@ -1127,8 +1418,15 @@ static TuneParams tune_params(Graph* g, const di_tune* tn, int mode, int precisi
   p.c = (tn && tn->c > 0.f) ? (double)tn->c : 1.0;
   const int tables = tn ? tn->tables : 0;
   DI_REQUIRE(tables >= 0 && tables <= 2, "tables must be 0, 1 or 2");
+  // The whole-graph window (single solves): when asked for, or autotuned.
+  const bool asked = tn && tn->window_log2 == DI_WINDOW_WHOLE;
+  const bool fits = g->n <= DI_SMALL_MAX_NODES && g->m < (1ll << 31);
+  if (asked && mode == DI_TUNE_SOLVE)
+    DI_REQUIRE(fits, "DI_WINDOW_WHOLE needs n <= DI_SMALL_MAX_NODES and fewer than 2^31 links");
+  p.whole = mode == DI_TUNE_SOLVE && asked;
   p.gt = false;
-  p.wlog = window_log2_for(g->n, tn ? tn->window_log2 : 0, tables, &p.gt);
+  p.wlog = window_log2_for(g->n, p.whole ? 14 : (tn && !asked ? tn->window_log2 : 0), tables,
+                           &p.gt);
   DI_REQUIRE(p.wlog > 0, "graph has too many nodes for the window tables");
   p.check_every = tn ? std::max(0, tn->check_every) : 0;
   p.threads = tn && tn->threads ? tn->threads : kRoundThreads;
@@ -1189,7 +1487,8 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   }
   k_init<T><<<dim3(grid_for(g->n, 2048), 1), kBlock, 0, s>>>(a, vdev, resume ? 1 : 0, 0);
   DI_HIP(hipGetLastError());
-  run_rounds(a, ws, tp.sched, tp.check_every, s, &lt);
+  if (tp.whole) launch_small(a, ws, tp.sched, s, &lt);
+  else run_rounds(a, ws, tp.sched, tp.check_every, s, &lt);
   double* xo = x ? (dev ? x : ws->x.as<double>()) : nullptr;
   flush(a, xo, o->normalize, s);
   const double secs = timer.stop();
@@ -1198,8 +1497,9 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   const Ctl* h = ws->hctl.as<Ctl>();
   if (st) {
     fill_stats(*h, o, secs, st);
-    // launches 0..stop_round take and expand; launch stop_round+1 folds.
-    const size_t working = (size_t)h->stop_round + 2;
+    // launches 0..stop_round take and expand; launch stop_round+1 folds (the
+    // whole-graph window: one launch).
+    const size_t working = tp.whole ? 1 : (size_t)h->stop_round + 2;
     st->kernel_seconds = lt.on ? lt.total(working) : 0.0;
     st->kernel_launches = lt.on ? (int64_t)working : 0;
   }

@@ -219,6 +219,12 @@ di_status di_window_layout(int64_t n, const di_tune* tune, int32_t* window_log2,
     DI_REQUIRE(n >= 1 && n < (1ll << 31), "n must be in [1, 2^31)");
     const int tables = tune ? tune->tables : 0;
     DI_REQUIRE(tables >= 0 && tables <= 2, "tables must be 0, 1 or 2");
+    if (tune && tune->window_log2 == DI_WINDOW_WHOLE) {
+      DI_REQUIRE(n <= DI_SMALL_MAX_NODES, "DI_WINDOW_WHOLE needs n <= DI_SMALL_MAX_NODES");
+      *window_log2 = DI_WINDOW_WHOLE;
+      *global_tables = 0;
+      return;
+    }
     bool gt = false;
     const int k = window_log2_for(n, tune ? tune->window_log2 : 0, tables, &gt);
     DI_REQUIRE(k > 0, "graph has too many nodes for the window tables");

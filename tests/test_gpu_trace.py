@@ -27,7 +27,8 @@ def di():
     ("pagerank-10k", "fp64", 1e-10, "op"),
     ("rand", "fp64", 1e-10, "op2"),
 ])
-def test_replay_of_recorded_sets(di, gname, prec, tol, sched):
+@pytest.mark.parametrize("win", [0, -1], ids=["windows", "whole"])
+def test_replay_of_recorded_sets(di, gname, prec, tol, sched, win):
     import torch
     g = wl.recipe(gname) if gname != "rand" else wl.random_small(5000, 40000, seed=41, p_dangling=0.2)
     G = di.Graph(g)
@@ -37,7 +38,7 @@ def test_replay_of_recorded_sets(di, gname, prec, tol, sched):
     F0 = F.cpu().numpy().astype(np.float64)
     trace = torch.zeros((400, g.n), dtype=torch.uint8, device="cuda")
     _, st = di.solve(G, d=D, tol=tol, precision=prec, state=(F, H), trace=trace,
-                     tune=di.make_tune(sched, 1.0))
+                     tune=di.make_tune(sched, 1.0, window_log2=win))
     rounds = st["rounds"]
     assert 0 < rounds <= 400
     sets = trace[:rounds].cpu().numpy().astype(bool)
@@ -74,7 +75,8 @@ def _score(sched, F, outdeg, indeg):
     ("rand", "op", 1.0),
     ("rand", "op2", 0.5),
 ])
-def test_every_round_takes_the_top_of_its_score(di, gname, sched, c):
+@pytest.mark.parametrize("win", [0, -1], ids=["windows", "whole"])
+def test_every_round_takes_the_top_of_its_score(di, gname, sched, c, win):
     """Every round of a traced fp64 solve takes an upper set of the schedule's
     score: on the oracle's replay of the recorded sets, each round's lowest
     taken score is at least the highest score of the nodes it left holding
@@ -90,7 +92,7 @@ def test_every_round_takes_the_top_of_its_score(di, gname, sched, c):
     F0 = F.cpu().numpy()
     trace = torch.zeros((600, g.n), dtype=torch.uint8, device="cuda")
     _, st = di.solve(G, d=D, tol=1e-10, precision="fp64", state=(F, H), trace=trace,
-                     tune=di.make_tune(sched, c))
+                     tune=di.make_tune(sched, c, window_log2=win))
     rounds = st["rounds"]
     assert 0 < rounds <= 600
     sets = trace[:rounds].cpu().numpy().astype(bool)
