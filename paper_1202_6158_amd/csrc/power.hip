@@ -88,6 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_pull(PowArgs<G> a, int k) {
   if (__hip_atomic_load(&ctl->done_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= 0) return;
   __shared__ double s_val[kPullNnz];
   __shared__ double s_red[kBlock / 64];
+  __shared__ int s_long[kPullRows];  // rows of this block summed by a wave
+  __shared__ int s_nlong;
   if (k >= 1) {
     const double res = block_sum(ctl->acc[(k - 1) % 3][threadIdx.x], s_red);
     int reason = 0;
@@ -133,6 +135,8 @@ __global__ __launch_bounds__(kBlock) void k_pull(PowArgs<G> a, int k) {
     return t;
   };
   constexpr int kGU = 4;
+  constexpr int kGB = 8;         // gathers in flight per thread (row blocks)
+  constexpr int kShortRow = 32;  // rows longer than this are summed by a wave
   if (r1 - r0 == 1 && e1 - e0 > kPullNnz) {
     double acc = 0.0;
     for (int64_t e00 = e0 + threadIdx.x; e00 < e1; e00 += kGU * kBlock) {
@@ -155,29 +159,51 @@ __global__ __launch_bounds__(kBlock) void k_pull(PowArgs<G> a, int k) {
     acc = block_sum(acc, s_red);
     if (threadIdx.x == 0) finish_row(r0, acc);
   } else {
-    for (int64_t e00 = e0 + threadIdx.x; e00 < e1; e00 += kGU * kBlock) {
-      int32_t src[kGU];
+    // this thread's row's in-link range, loaded beside the gathers
+    const int r = r0 + threadIdx.x;
+    int64_t rb = 0, rc = 0;
+    if (r < r1) {
+      rb = a.in_ptr[r] - e0;
+      rc = a.in_ptr[r + 1] - e0;
+    }
+    for (int64_t e00 = e0 + threadIdx.x; e00 < e1; e00 += kGB * kBlock) {
+      int32_t src[kGB];
 #pragma unroll
-      for (int q = 0; q < kGU; ++q) {
+      for (int q = 0; q < kGB; ++q) {
         const int64_t e = e00 + (int64_t)q * kBlock;
         src[q] = e < e1 ? a.in_src[e] : -1;
       }
-      double t[kGU];
+      double t[kGB];
 #pragma unroll
-      for (int q = 0; q < kGU; ++q) t[q] = src[q] >= 0 ? (double)xs[src[q]] : 0.0;
+      for (int q = 0; q < kGB; ++q) t[q] = src[q] >= 0 ? (double)xs[src[q]] : 0.0;
 #pragma unroll
-      for (int q = 0; q < kGU; ++q) {
+      for (int q = 0; q < kGB; ++q) {
         const int64_t e = e00 + (int64_t)q * kBlock;
         if (src[q] >= 0) s_val[e - e0] = kWeighted ? t[q] * a.in_w[e] : t[q];
       }
     }
+    if (threadIdx.x == 0) s_nlong = 0;
     __syncthreads();
-    const int r = r0 + threadIdx.x;
+    // Short rows: summed by their own thread.  Longer ones are listed and
+    // each summed by a whole wave, so that no thread walks a hub row alone.
     if (r < r1) {
+      if (rc - rb <= kShortRow) {
+        double acc = 0.0;
+        for (int64_t q = rb; q < rc; ++q) acc += s_val[q];
+        finish_row(r, acc);
+      } else {
+        s_long[atomicAdd(&s_nlong, 1)] = r;
+      }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = wid; k < s_nlong; k += kBlock / 64) {
+      const int rr = s_long[k];
+      const int64_t b = a.in_ptr[rr] - e0, c = a.in_ptr[rr + 1] - e0;
       double acc = 0.0;
-      const int64_t b = a.in_ptr[r] - e0, c = a.in_ptr[r + 1] - e0;
-      for (int64_t q = b; q < c; ++q) acc += s_val[q];
-      finish_row(r, acc);
+      for (int64_t q = b + lane; q < c; q += 64) acc += s_val[q];
+      acc = wave_sum(acc);
+      if (lane == 0) finish_row(rr, acc);
     }
   }
   (void)gather;
