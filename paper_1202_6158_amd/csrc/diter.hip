@@ -1911,6 +1911,8 @@ int64_t slot_bytes(const Graph* g, int precision) {
   return bytes_per_vector(g->n, g->m, nb, precision);
 }
 
+constexpr int kMaxStepRounds = 16;  // rounds an engine step may launch
+
 template <typename T>
 class SlotPoolT : public SlotPool {
  public:
@@ -1921,11 +1923,11 @@ class SlotPoolT : public SlotPool {
     d_.assign(capacity, 0.85);
     tol_.assign(capacity, 1e-6);
     vmap_.alloc(capacity * 4);
-    vround_.alloc(capacity * 4);
+    vround_.alloc((size_t)kMaxStepRounds * capacity * 4);
     vd_.alloc(capacity * 8);
     vtol_.alloc(capacity * 8);
     h_vmap_.alloc(capacity * 4);
-    h_vround_.alloc(capacity * 4);
+    h_vround_.alloc((size_t)kMaxStepRounds * capacity * 4);
     h_vd_.alloc(capacity * 8);
     h_vtol_.alloc(capacity * 8);
     topk_.reserve(capacity);
@@ -1987,19 +1989,24 @@ class SlotPoolT : public SlotPool {
     DI_HIP(hipStreamSynchronize(s));
   }
 
-  void step(const std::vector<int>& slots, hipStream_t s) override {
-    if (slots.empty()) return;
+  void step(const std::vector<int>& slots, int rounds, hipStream_t s) override {
+    if (slots.empty() || rounds < 1) return;
+    DI_REQUIRE(rounds <= kMaxStepRounds, "too many rounds per engine step");
     const int k = (int)slots.size();
     int32_t* hv = h_vmap_.as<int32_t>();
-    int32_t* hr = h_vround_.as<int32_t>();
+    int32_t* hr = h_vround_.as<int32_t>();  // [rounds][cap]: launch i runs round round_[q] + i
     for (int q = 0; q < k; ++q) hv[q] = slots[q];
-    for (int q = 0; q < cap_; ++q) hr[q] = round_[q];
+    for (int i = 0; i < rounds; ++i)
+      for (int q = 0; q < cap_; ++q) hr[i * cap_ + q] = round_[q] + i;
     DI_HIP(hipMemcpyAsync(vmap_.p, h_vmap_.p, k * 4, hipMemcpyHostToDevice, s));
-    DI_HIP(hipMemcpyAsync(vround_.p, h_vround_.p, cap_ * 4, hipMemcpyHostToDevice, s));
+    DI_HIP(hipMemcpyAsync(vround_.p, h_vround_.p, (size_t)rounds * cap_ * 4,
+                          hipMemcpyHostToDevice, s));
     DiArgs<T> a = args(k);
-    a.vround = vround_.as<int32_t>();
-    launch_round(a, tp_.sched, 0, 0, s);
-    for (int q : slots) ++round_[q];
+    for (int i = 0; i < rounds; ++i) {
+      a.vround = vround_.as<int32_t>() + (size_t)i * cap_;
+      launch_round(a, tp_.sched, 0, 0, s);
+    }
+    for (int q : slots) round_[q] += rounds;
   }
 
   std::vector<int> stopped(const std::vector<int>& slots, hipStream_t s) override {

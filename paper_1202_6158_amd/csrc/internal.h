@@ -185,8 +185,9 @@ class SlotPool {
   virtual int64_t bytes() const = 0;
   // Initialise the slots of `inits` (F = (1-d)V, H = 0, control reset).
   virtual void admit(const std::vector<SlotInit>& inits, hipStream_t s) = 0;
-  // One round for every listed slot (each at its own round index).
-  virtual void step(const std::vector<int>& slots, hipStream_t s) = 0;
+  // `rounds` rounds in a row for every listed slot (each at its own round
+  // index; a slot whose solve stops within them returns at once afterwards).
+  virtual void step(const std::vector<int>& slots, int rounds, hipStream_t s) = 0;
   // Refresh the host copy of the slots' control blocks (synchronises s) and
   // return the slots among `slots` whose solve has stopped.
   virtual std::vector<int> stopped(const std::vector<int>& slots, hipStream_t s) = 0;

@@ -3,7 +3,7 @@
 // Requests (a seed set, d, tol) are queued per graph.  Every graph has an
 // engine thread and a HIP stream of its own; the thread repeats one engine
 // step: admit queued requests into free slots of the graph's slot pool
-// (device state sized from the HBM budget), run one D-iteration round for
+// (device state sized from the HBM budget), run a few D-iteration rounds for
 // every active slot (slots admitted at different times sit at different rounds
 // of their own solves and share each launch), detect the slots whose solve
 // stopped, flush them, take their top-k on the device and complete the
@@ -27,6 +27,12 @@
 namespace di {
 
 namespace {
+
+// Rounds an engine step launches before it reads the slots' control blocks:
+// one host round trip per four rounds instead of per round; a request that
+// stops inside a step waits at most three rounds (launches that return at
+// once) for its result.
+constexpr int kStepRounds = 4;
 
 struct Request {
   uint64_t id = 0;
@@ -150,7 +156,7 @@ void Server::loop(int gi) {
     ++step_no;
     di_status rc = guarded([&] {
       ge.pool->admit(inits, ge.stream);
-      ge.pool->step(active, ge.stream);
+      ge.pool->step(active, kStepRounds, ge.stream);
       if (!active.empty()) {
         const std::vector<int> fin = ge.pool->stopped(active, ge.stream);
         ge.pool->finish(fin, opts.topk, results, ge.stream);
