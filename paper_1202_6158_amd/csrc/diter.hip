@@ -507,8 +507,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   mrem = 0.0;  // now: the largest untaken score of this window
   // A. Decide for every node of the window (LDS only) before any push, so a
   //    round takes one set S (reading 5) even though pushes that stay inside
-  //    the window are applied to its LDS copy at once.
-  for (int q = tid; q < W; q += kRT) {
+  //    the window are applied to its LDS copy at once.  Bit k of tbits: this
+  //    thread's k-th node was taken; s_chunk: taken nodes per 64-node chunk.
+  int32_t* const s_chunk = s_beo;                          // [W/64], free until the first pass
+  uint16_t* const s_list = reinterpret_cast<uint16_t*>(s_bsh);  // [kSuper], same
+  uint32_t tbits = 0;
+  for (int q = tid, k = 0; q < W; q += kRT, ++k) {
     // Fluid may be signed after an update of the graph (Section 3.2): the
     // threshold and the residual use |F_i|.
     const double f = q < wn ? win[q] : 0.0, af = fabs(f);
@@ -527,18 +531,44 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       acc[0] = NAN;
     }
     s_state[q] = st;
+    tbits |= (uint32_t)st << k;
+    const unsigned long long m = __ballot(st != 0);
+    if ((tid & 63) == 0) s_chunk[q >> 6] = __popcll(m);
   }
   __syncthreads();
+  // When at most one pass worth of nodes is taken, list them in node order
+  // (chunk offsets plus the rank within the chunk) and run a single pass over
+  // the list; otherwise every pass walks kSuper consecutive nodes.
+  const long long ntk = lds_exscan<kRT>(s_chunk, W >> 6, s_scr);
+  const bool use_list = ntk <= kSuper;
+  if (use_list && ntk > 0) {
+    for (int q = tid, k = 0; q < W; q += kRT, ++k) {
+      const bool t = (tbits >> k) & 1u;
+      const unsigned long long m = __ballot(t);
+      const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+      if (t) s_list[s_chunk[q >> 6] + rank] = (uint16_t)q;
+    }
+    __syncthreads();
+  }
+  const int tlim = use_list ? (int)ntk : wn;
   int local_push = 0;  // some push stayed inside the window (its fluid is in LDS)
-  for (int t0 = 0; t0 < wn; t0 += kSuper) {
-    // B. Take the tile's nodes of S: load their link ranges and histories.
+  for (int t0 = 0; t0 < tlim; t0 += kSuper) {
+    // B. Take the pass's nodes of S: load their link ranges and histories.
     double f[kNPT];
     bool tk[kNPT];
+    int qs[kNPT];
 #pragma unroll
     for (int u = 0; u < kNPT; ++u) {
-      const int q = t0 + tid + u * kRT;
-      tk[u] = q < wn && s_state[q] == 1;
-      f[u] = tk[u] ? win[q] : 0.0;
+      const int i = t0 + tid + u * kRT;
+      if (use_list) {
+        tk[u] = i < tlim;
+        qs[u] = tk[u] ? (int)s_list[i] : 0;
+      } else {
+        qs[u] = i;
+        tk[u] = i < wn && s_state[i] == 1;
+      }
+      f[u] = tk[u] ? win[qs[u]] : 0.0;
     }
     int64_t rs[kNPT];
     int dgs[kNPT];
@@ -546,7 +576,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int u = 0; u < kNPT; ++u) {
       if (!tk[u]) continue;
-      const int64_t j = j0 + t0 + tid + u * kRT;
+      const int64_t j = j0 + qs[u];
       rs[u] = a.row_ptr[j];
       dgs[u] = a.deg[j];
       h[u] = Hv[j];
@@ -555,7 +585,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int u = 0; u < kNPT; ++u) {
       if (!tk[u]) continue;
-      const int q = t0 + tid + u * kRT;
+      const int q = qs[u];
       Hv[j0 + q] = h[u] + f[u];
       win[q] = 0.0;
       s_state[q] = 2;
