@@ -298,8 +298,9 @@ typedef struct di_tune_trial {
  * scatter for this graph by timing trial solves on the device: first every
  * schedule x c in {1/32, 1/16, 1/8, 1/4, 1/2, 1, 2} at the default window,
  * then the best pair at larger and smaller windows, one size at a time in
- * each direction while the time improves, then the winner with 1024-thread
- * workgroups; for DI_TUNE_SOLVE on a graph of at most DI_SMALL_MAX_NODES
+ * each direction while the time improves, then the three fastest pairs of
+ * the first step at the chosen window with 1024-thread workgroups; for
+ * DI_TUNE_SOLVE on a graph of at most DI_SMALL_MAX_NODES
  * nodes, also every schedule x c in the whole-graph window (DI_WINDOW_WHOLE).
  * Any schedule converges to the same limit (the order
  * independence of Sections 2.2 and 3.1), so only speed is compared.

@@ -107,10 +107,12 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
     // 1. schedule x threshold factor at the default window
     const int scheds[] = {DI_SCHED_MEAN, DI_SCHED_OP2, DI_SCHED_OP};
     const float cs[] = {0.03125f, 0.0625f, 0.125f, 0.25f, 0.5f, 1.0f, 2.0f};
+    std::vector<Trial> step1{win};
     for (int sc : scheds)
       for (float c : cs) {
         if (sc == DI_SCHED_MEAN && c == 1.0f) continue;  // step 0
         const Trial t = run(sc, c, w0);
+        step1.push_back(t);
         if (better(t, win)) win = t;
       }
     // 2. window size for the best pair: walk from the default in each
@@ -129,10 +131,16 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
         }
       }
     }
-    // 3. the winner with 1024-thread workgroups
+    // 3. 1024-thread workgroups at the chosen window, for the three fastest
+    //    (schedule, c) pairs of step 1: with more threads per window the best
+    //    threshold factor can differ
     if (win.status == DI_OK) {
-      const Trial t = run(win.tune.schedule, win.tune.c, win.tune.window_log2, 1024);
-      if (better(t, win)) win = t;
+      std::stable_sort(step1.begin(), step1.end(), better);
+      const int wl = win.tune.window_log2;
+      for (size_t k = 0; k < step1.size() && k < 3 && step1[k].status == DI_OK; ++k) {
+        const Trial t = run(step1[k].tune.schedule, step1[k].tune.c, wl, 1024);
+        if (better(t, win)) win = t;
+      }
     }
     // 4. single solves on graphs that one workgroup's LDS holds: the
     //    whole-graph window at every schedule x threshold factor

@@ -91,6 +91,7 @@ struct DiArgs {
   int weighted;
   int threads;  // round workgroup size (host side: selects the kernel instance)
   int gt;       // segment tables in global memory (host side: selects the kernel instance)
+  int wlist;    // LDS holds a list of the whole window (2 bytes per node) after the state bytes
   uint8_t* trace;        // [trace_rounds][n] taken sets of a traced solve (NULL: none)
   int64_t trace_rounds;
 };
@@ -509,8 +510,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   //    round takes one set S (reading 5) even though pushes that stay inside
   //    the window are applied to its LDS copy at once.  Bit k of tbits: this
   //    thread's k-th node was taken; s_chunk: taken nodes per 64-node chunk.
-  int32_t* const s_chunk = s_beo;                          // [W/64], free until the first pass
-  uint16_t* const s_list = reinterpret_cast<uint16_t*>(s_bsh);  // [kSuper], same
+  int32_t* const s_chunk = s_beo;  // [W/64], free until the first pass
+  // the taken list: [W] after the state bytes when the launch has room for
+  // it, else [kSuper] in the staging area (free until the first pass's staging)
+  uint16_t* const s_list = a.wlist ? reinterpret_cast<uint16_t*>(s_state + W)
+                                   : reinterpret_cast<uint16_t*>(s_bsh);
+  const int list_cap = a.wlist ? W : kSuper;
   uint32_t tbits = 0;
   for (int q = tid, k = 0; q < W; q += kRT, ++k) {
     // Fluid may be signed after an update of the graph (Section 3.2): the
@@ -536,11 +541,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     if ((tid & 63) == 0) s_chunk[q >> 6] = __popcll(m);
   }
   __syncthreads();
-  // When at most one pass worth of nodes is taken, list them in node order
-  // (chunk offsets plus the rank within the chunk) and run a single pass over
-  // the list; otherwise every pass walks kSuper consecutive nodes.
+  // When the list can hold them, list the taken nodes in node order (chunk
+  // offsets plus the rank within the chunk) and run the passes over the list;
+  // otherwise every pass walks kSuper consecutive nodes.
   const long long ntk = lds_exscan<kRT>(s_chunk, W >> 6, s_scr);
-  const bool use_list = ntk <= kSuper;
+  const bool use_list = ntk <= list_cap;
   if (use_list && ntk > 0) {
     for (int q = tid, k = 0; q < W; q += kRT, ++k) {
       const bool t = (tbits >> k) & 1u;
@@ -959,10 +964,13 @@ static int grid_for(int64_t n, int cap) {
 }
 
 template <typename T, int SCHED, int NT, bool GT = false>
-static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, LaunchTimer* lt) {
-  const size_t smem = round_lds_bytes(a.wlog, a.nb, GT);
+static void launch_round_t(const DiArgs<T>& a0, int r, int mode, hipStream_t s, LaunchTimer* lt) {
+  DiArgs<T> a = a0;
+  size_t smem = round_lds_bytes(a.wlog, a.nb, GT);
   // Dynamic LDS may use what the static part leaves of the workgroup limit
   // (set once per kernel instance; thread-safe initialisation).
+  // (The LDS limit of a workgroup is the LDS of a CU on gfx950.)
+  static size_t lds_cu = 0;
   static const size_t dyn_limit = [] {
     hipFuncAttributes fa;
     DI_HIP(hipFuncGetAttributes(&fa, (const void*)k_round<T, SCHED, NT, GT>));
@@ -972,9 +980,20 @@ static void launch_round_t(const DiArgs<T>& a, int r, int mode, hipStream_t s, L
     const size_t dl = (size_t)lim - fa.sharedSizeBytes;
     DI_HIP(hipFuncSetAttribute((const void*)k_round<T, SCHED, NT, GT>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl));
+    lds_cu = (size_t)lim;
     return dl;
   }();
   DI_REQUIRE(smem <= dyn_limit, "window tables exceed the LDS available to the round kernel");
+  // A taken list of the whole window (2 bytes per node) when it fits and
+  // costs no workgroups per CU (registers allow two 512-thread or one
+  // 1024-thread workgroup).
+  const size_t stat = lds_cu - dyn_limit;  // static LDS of this instance
+  auto per_cu = [&](size_t dyn) {
+    return std::min<size_t>(NT == 512 ? 2 : 1, lds_cu / (dyn + stat));
+  };
+  const size_t list_bytes = (size_t)2 << a.wlog;
+  a.wlist = smem + list_bytes <= dyn_limit && per_cu(smem + list_bytes) >= per_cu(smem) ? 1 : 0;
+  if (a.wlist) smem += list_bytes;
   const dim3 grid(a.nb, a.nvec);
   if (lt && lt->on) {
     // The runtime stamps the kernel's own begin/end into the event pair.
