@@ -166,6 +166,17 @@ di_status di_window_layout(int64_t n, const di_tune* tune, int32_t* window_log2,
                            int32_t* global_tables);
 di_status di_graph_info(const di_graph* g, int64_t* n, int64_t* nnz, int64_t* n_dangling);
 
+/*
+ * Diagnostic switch, process-wide, for tests of a fallback path.  The round
+ * kernel lists each window's taken nodes in LDS and expands them 1024 at a
+ * time; when LDS has no room for the list (graphs near the size limit) it
+ * expands passes of 1024 consecutive nodes instead.  enable = 0 forces that
+ * fallback for every later launch, 1 (the default) restores the list.  It
+ * changes the order in which a round's pushes are issued, not the set a
+ * round takes.  DI_EINVAL unless enable is 0 or 1.  Host only.
+ */
+di_status di_set_taken_list(int32_t enable);
+
 /* --------------------------------------------------------- single solves */
 
 /*

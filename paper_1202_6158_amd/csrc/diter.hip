@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -91,7 +92,7 @@ struct DiArgs {
   int weighted;
   int threads;  // round workgroup size (host side: selects the kernel instance)
   int gt;       // segment tables in global memory (host side: selects the kernel instance)
-  int wlist;    // LDS holds a list of the whole window (2 bytes per node) after the state bytes
+  int wlist;    // taken list: 1 whole window (after the state bytes), 0 one pass (staging), 2 none
   uint8_t* trace;        // [trace_rounds][n] taken sets of a traced solve (NULL: none)
   int64_t trace_rounds;
 };
@@ -513,9 +514,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   int32_t* const s_chunk = s_beo;  // [W/64], free until the first pass
   // the taken list: [W] after the state bytes when the launch has room for
   // it, else [kSuper] in the staging area (free until the first pass's staging)
-  uint16_t* const s_list = a.wlist ? reinterpret_cast<uint16_t*>(s_state + W)
-                                   : reinterpret_cast<uint16_t*>(s_bsh);
-  const int list_cap = a.wlist ? W : kSuper;
+  uint16_t* const s_list = a.wlist == 1 ? reinterpret_cast<uint16_t*>(s_state + W)
+                                        : reinterpret_cast<uint16_t*>(s_bsh);
+  const int list_cap = a.wlist == 1 ? W : a.wlist == 0 ? kSuper : 0;
   uint32_t tbits = 0;
   for (int q = tid, k = 0; q < W; q += kRT, ++k) {
     // Fluid may be signed after an update of the graph (Section 3.2): the
@@ -963,6 +964,9 @@ static int grid_for(int64_t n, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
 }
 
+// Diagnostic switch (di_set_taken_list): 0 forces passes over consecutive nodes.
+static std::atomic<int> g_taken_list{1};
+
 template <typename T, int SCHED, int NT, bool GT = false>
 static void launch_round_t(const DiArgs<T>& a0, int r, int mode, hipStream_t s, LaunchTimer* lt) {
   DiArgs<T> a = a0;
@@ -992,8 +996,12 @@ static void launch_round_t(const DiArgs<T>& a0, int r, int mode, hipStream_t s, 
     return std::min<size_t>(NT == 512 ? 2 : 1, lds_cu / (dyn + stat));
   };
   const size_t list_bytes = (size_t)2 << a.wlog;
-  a.wlist = smem + list_bytes <= dyn_limit && per_cu(smem + list_bytes) >= per_cu(smem) ? 1 : 0;
-  if (a.wlist) smem += list_bytes;
+  if (!g_taken_list.load(std::memory_order_relaxed)) {
+    a.wlist = 2;
+  } else {
+    a.wlist = smem + list_bytes <= dyn_limit && per_cu(smem + list_bytes) >= per_cu(smem) ? 1 : 0;
+    if (a.wlist == 1) smem += list_bytes;
+  }
   const dim3 grid(a.nb, a.nvec);
   if (lt && lt->on) {
     // The runtime stamps the kernel's own begin/end into the event pair.
@@ -2184,6 +2192,13 @@ di_status di_solve_batch(const di_graph* gc, int32_t B, const int64_t* seed_ptr,
              : batch_impl<float>(g, B, seed_ptr, seeds, seed_w, opts, x, stats, s);
   });
   return g != DI_OK ? g : rc;
+}
+
+di_status di_set_taken_list(int32_t enable) {
+  return guarded([&] {
+    DI_REQUIRE(enable == 0 || enable == 1, "enable must be 0 or 1");
+    g_taken_list.store(enable, std::memory_order_relaxed);
+  });
 }
 
 di_status di_diffuse_round(const di_graph* gc, int32_t precision, double d, double theta,

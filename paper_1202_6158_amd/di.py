@@ -113,6 +113,7 @@ _SIGS = {
     "di_graph_destroy": [_P],
     "di_graph_info": [_P, _P, _P, _P],
     "di_window_layout": [ctypes.c_int64, ctypes.POINTER(Tune), _P, _P],
+    "di_set_taken_list": [ctypes.c_int32],
     "di_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_power_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_power_solve_noalloc": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
@@ -151,6 +152,12 @@ def last_error() -> str:
 
 def version() -> str:
     return _lib.di_version().decode()
+
+
+def set_taken_list(enable: bool):
+    """di_set_taken_list: diagnostic, process-wide; False forces the round
+    kernel's fallback of passes over consecutive nodes."""
+    _check(_lib.di_set_taken_list(1 if enable else 0))
 
 
 def window_layout(n: int, tune=None):

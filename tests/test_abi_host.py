@@ -117,3 +117,11 @@ def test_window_layout_rejects_what_does_not_fit(n, tables):
     with pytest.raises(di.DiError) as e:
         di.window_layout(n, di.make_tune("mean", 1.0, tables=tables))
     assert e.value.status == di.EINVAL
+
+
+def test_taken_list_switch_is_host_only_and_checked():
+    from paper_1202_6158_amd import di
+    assert di._lib.di_set_taken_list(2) == di.EINVAL and "enable" in di.last_error()
+    assert di._lib.di_set_taken_list(-1) == di.EINVAL
+    di.set_taken_list(False)
+    di.set_taken_list(True)
