@@ -532,6 +532,33 @@ def _run_stream(di, srv, gids, graphs, t, gi, sizes, tol, sub, d, label):
     return res, sub_s
 
 
+def run_section_child(name, args, forward):
+    """Runs one section of this script in a child process (same interpreter,
+    same flags as given in `forward`) and returns its result; a crash or a
+    time-out there loses that section only, reported as an error."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--section", name] + forward
+    log("section %s in a child process" % name)
+    try:
+        p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=1200)
+    except subprocess.TimeoutExpired:
+        return {"error": "section %s timed out" % name}
+    lines = [ln for ln in p.stdout.splitlines() if ln.startswith("{")]
+    if p.returncode != 0 or not lines:
+        return {"error": "section %s exited with status %d" % (name, p.returncode)}
+    return json.loads(lines[-1])["result"]
+
+
+def serve_forward(args):
+    """The command-line flags of the serving section."""
+    f = ["--d", repr(args.d), "--serve-rate", repr(args.serve_rate),
+         "--serve-seconds", repr(args.serve_seconds),
+         "--serve-sustained-seconds", repr(args.serve_sustained_seconds),
+         "--serve-warmup", repr(args.serve_warmup), "--serve-burst", str(args.serve_burst),
+         "--serve-solo", str(args.serve_solo), "--serve-hbm-gib", str(args.serve_hbm_gib)]
+    return f + (["--no-autotune"] if args.no_autotune else [])
+
+
 def bench_serve(di, args):
     """Continuous-batching server on the four resident serving graphs: an
     open-loop Poisson stream (latency percentiles, achieved rate), a burst of
@@ -717,10 +744,12 @@ def main():
     from paper_1202_6158_amd import di
     torch.cuda.set_device(0)
 
-    log("generating", args.workload)
-    g = wl.recipe(args.workload)
-    G = di.Graph(g)
-    log("graph n=%d links=%d dangling=%d" % (g.n, g.m, g.n_dangling))
+    g = G = None
+    if args.section in (None, "ppr", "update"):
+        log("generating", args.workload)
+        g = wl.recipe(args.workload)
+        G = di.Graph(g)
+        log("graph n=%d links=%d dangling=%d" % (g.n, g.m, g.n_dangling))
     if args.section:
         part = {"ppr": lambda: bench_ppr_batch(di, G, g, args),
                 "serve": lambda: bench_serve(di, args),
@@ -850,7 +879,9 @@ def main():
     if not args.no_replay:
         out["paper_replay"] = bench_paper_replay(di, args)
     if not args.no_serve:
-        out["serve"] = bench_serve(di, args)
+        # in a process of its own: four engine threads and their streams, the
+        # longest section; a failure there must not cost the other results
+        out["serve"] = run_section_child("serve", args, serve_forward(args))
     if not args.no_c3:
         del G
         torch.cuda.empty_cache()

@@ -29,6 +29,26 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
+def test_section_child_failure_is_reported_not_raised(bench):
+    """A section run in a child process that fails comes back as an error
+    entry (here: the child refuses a second GPU before touching any)."""
+    r = bench.run_section_child("serve", None, ["--gpus", "2"])
+    assert r == {"error": "section serve exited with status 2"}
+
+
+def test_serving_flags_are_accepted_by_the_child(bench):
+    import argparse
+    args = argparse.Namespace(d=0.85, serve_rate=2000.0, serve_seconds=5.0,
+                              serve_sustained_seconds=60.0, serve_warmup=1.0, serve_burst=2000,
+                              serve_solo=100, serve_hbm_gib=32, no_autotune=True)
+    f = bench.serve_forward(args)
+    assert "--no-autotune" in f
+    # parsed by the child's own argument parser (then refused at the GPU guard)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--section", "serve",
+                        "--gpus", "2"] + f, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "exactly one GPU" in r.stderr
+
+
 def test_algorithmic_bytes(bench):
     st = {"rounds": 3, "nodes_diffused": 10, "edges_diffused": 100}
     # fp32: 4 B per node scanned per round, 52 B per taken node, 12 B per link
