@@ -14,8 +14,9 @@
 //      (Theorem 2), the predicted remaining fluid and theta_r;
 //   2. folds the pushes of round r-1 addressed to window b into an fp64 LDS
 //      copy of its fluid (LDS atomics: a node hit k times is rounded once);
-//   3. takes the nodes reaching theta_r and expands their out-links at once,
-//      writing (local index, value) records into per-(source window,
+//   3. takes the nodes reaching theta_r (listed in node order in LDS) and
+//      expands their out-links at once, 1024 nodes per pass, writing
+//      (local index, value) records into per-(source window,
 //      destination window) segments.  A segment's place and size are fixed by
 //      the graph (the number of links between the two windows), so a record's
 //      slot is the segment start plus an LDS rank: no global atomics, no
@@ -26,9 +27,9 @@
 // once.  The host launches rounds in chunks and reads the control block
 // between chunks.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
-#include <atomic>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -433,7 +434,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const int q = tid + k * kRT;
     if (q < wn) win[q] = (double)fv[k];
   }
-  for (int q = tid + kWinPer * kRT; q < wn; q += kRT) win[q] = (double)Fv[j0 + q];
+  // the rest of a large window, kWinPer values per thread at a time
+  for (int q0 = tid + kWinPer * kRT; q0 < wn; q0 += kWinPer * kRT) {
+    T fr[kWinPer];
+#pragma unroll
+    for (int k = 0; k < kWinPer; ++k) {
+      const int q = q0 + k * kRT;
+      fr[k] = q < wn ? Fv[j0 + q] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < kWinPer; ++k) {
+      const int q = q0 + k * kRT;
+      if (q < wn) win[q] = (double)fr[k];
+    }
+  }
   if (tid < nb) {
     s_pre[tid] = c_own;
     if constexpr (!GT) {
@@ -518,28 +532,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                                         : reinterpret_cast<uint16_t*>(s_bsh);
   const int list_cap = a.wlist == 1 ? W : a.wlist == 0 ? kSuper : 0;
   uint32_t tbits = 0;
-  for (int q = tid, k = 0; q < W; q += kRT, ++k) {
-    // Fluid may be signed after an update of the graph (Section 3.2): the
-    // threshold and the residual use |F_i|.
-    const double f = q < wn ? win[q] : 0.0, af = fabs(f);
-    uint8_t st = 0;
-    if (af > 0.0) {
-      const int64_t j = j0 + q;
-      acc[0] += af;
-      acc[4] += 1.0;
-      int dg = -1;
-      if (SCHED != DI_SCHED_MEAN) dg = a.deg[j];
-      const double sc = node_score<SCHED>(af, dg, SCHED == DI_SCHED_OP ? a.indeg[j] : 0);
-      acc[3] += sc;
-      if (sc >= theta) st = 1;
-      else mrem = fmax(mrem, sc);
-    } else if (f != f) {
-      acc[0] = NAN;
+  // kDec nodes per thread at a time, so that their degree loads are in
+  // flight together (one wait per step, not per node)
+  constexpr int kDec = 4;
+  for (int q0 = tid, k0 = 0; q0 < W; q0 += kDec * kRT, k0 += kDec) {
+    double fq[kDec];
+    int dg[kDec], in[kDec];
+#pragma unroll
+    for (int u = 0; u < kDec; ++u) {
+      const int q = q0 + u * kRT;
+      fq[u] = q < wn ? win[q] : 0.0;
+      // unconditional loads (a clamped index past the window's end): no
+      // branch separates them, so they are all issued before the first wait
+      const int64_t j = j0 + min(q, wn - 1);
+      dg[u] = -1;
+      in[u] = 0;
+      if (SCHED != DI_SCHED_MEAN) dg[u] = a.deg[j];
+      if (SCHED == DI_SCHED_OP) in[u] = a.indeg[j];
     }
-    s_state[q] = st;
-    tbits |= (uint32_t)st << k;
-    const unsigned long long m = __ballot(st != 0);
-    if ((tid & 63) == 0) s_chunk[q >> 6] = __popcll(m);
+#pragma unroll
+    for (int u = 0; u < kDec; ++u) {
+      const int q = q0 + u * kRT;
+      if (q >= W) break;  // uniform in a wave
+      // Fluid may be signed after an update of the graph (Section 3.2): the
+      // threshold and the residual use |F_i|.
+      const double f = fq[u], af = fabs(f);
+      uint8_t st = 0;
+      if (af > 0.0) {
+        acc[0] += af;
+        acc[4] += 1.0;
+        const double sc = node_score<SCHED>(af, dg[u], in[u]);
+        acc[3] += sc;
+        if (sc >= theta) st = 1;
+        else mrem = fmax(mrem, sc);
+      } else if (f != f) {
+        acc[0] = NAN;
+      }
+      s_state[q] = st;
+      tbits |= (uint32_t)st << (k0 + u);
+      const unsigned long long m = __ballot(st != 0);
+      if ((tid & 63) == 0) s_chunk[q >> 6] = __popcll(m);
+    }
   }
   __syncthreads();
   // When the list can hold them, list the taken nodes in node order (chunk
