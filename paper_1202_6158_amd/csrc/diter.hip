@@ -355,49 +355,54 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   // Every load that does not depend on this round's decisions is issued
   // before the first wait: the stop flag, round r-1's sums, this window's
   // fluid, its incoming record counts and the tables of its outgoing segments.
-  const int sr = ld_relaxed(&ctl->stop_round);
+  // (a plain load of a uniform address, so a scalar one: waiting for it does
+  // not wait for the vector loads; a stop recorded by this very launch reads
+  // either way as "not earlier")
+  const int sr = ctl->stop_round;
   const Slot* P = slots + ((r + 2) % 3) * kSlots;  // set (r-1) % 3
-  double v[kSums] = {0, 0, 0, 0, 0, 0, 0};          // nf, snd, sd, ssc, nnz, taken, edges
-  double mrem = 0.0;
-  if (r >= 1 && tid < kSlots) {
-    const Slot p = P[tid];
-#pragma unroll
-    for (int f = 0; f < kSums; ++f) v[f] = p.sum[f];
-    mrem = __longlong_as_double((long long)p.mrem);
-  }
+  // These loads use clamped indices and no branch (the values past the ends
+  // are dropped later), so that none of them waits for another: a load in a
+  // branch whose value is used in it is followed by its own wait.
+  const Slot p_own = P[min(tid, kSlots - 1)];  // round r-1's sums, slot tid
   constexpr int kWinPer = 4;  // window values prefetched per thread (the rest load later)
   T fv[kWinPer];
 #pragma unroll
-  for (int k = 0; k < kWinPer; ++k) {
-    const int q = tid + k * kRT;
-    fv[k] = q < wn ? Fv[j0 + q] : (T)0;
-  }
+  for (int k = 0; k < kWinPer; ++k) fv[k] = Fv[j0 + min(tid + k * kRT, wn - 1)];
   const int was_active = a.active[(int64_t)vb * nb + b];
   int32_t* const cnt_in = a.cnt[(r - 1) & 1] + vb * nb2 + (int64_t)b * nb;
-  int32_t c_own = 0, o_own = 0, cap_own = 0;  // first pass over windows (nb <= kRT usually)
-  int64_t base_own = 0;
-  if (tid < nb) {
-    if (r >= 1) c_own = cnt_in[tid];
-    if constexpr (!GT) {
-      if (r >= 1) o_own = a.soff[(int64_t)b * nb + tid];
-      base_own = a.bstart[tid] + a.soffT[(int64_t)b * nb + tid];
-      cap_own = a.capT[(int64_t)b * nb + tid];
-    }
+  // first pass over the windows (nb <= kRT usually)
+  const int tw = min(tid, nb - 1);
+  const int32_t c_own = cnt_in[tw];
+  int32_t o_own = 0, cap_own = 0, sT_own = 0;
+  int64_t bs_own = 0;
+  if constexpr (!GT) {
+    o_own = a.soff[(int64_t)b * nb + tw];
+    bs_own = a.bstart[tw];
+    sT_own = a.soffT[(int64_t)b * nb + tw];
+    cap_own = a.capT[(int64_t)b * nb + tw];
   }
-  // Launch r itself records stop_round = r-1; an earlier stop ends this launch.
-  if (sr >= 0 && sr < r - 1) return;
+
+  // Launch r itself records stop_round = r-1; an earlier stop ends this
+  // launch.  Its writes below are skipped and it returns after them, so that
+  // the test does not hold back the loads above.
+  const bool ended = sr >= 0 && sr < r - 1;
 
   // 1. Decisions from round r-1's partial sums (identical in every workgroup).
   double theta = a.theta0;
   bool stop = mode == 1;
   if (r >= 1) {
-    if (b == 0 && tid < kSlots) {  // set (r+1) % 3 is next used by launch r+1
+    if (b == 0 && tid < kSlots && !ended) {  // set (r+1) % 3 is next used by launch r+1
       Slot* z = slots + ((r + 1) % 3) * kSlots + tid;
 #pragma unroll
       for (int f = 0; f < kSums; ++f) z->sum[f] = 0.0;
       z->mrem = 0;
     }
-    block_reduce_k<kRT, kSums>(v, mrem, s_red);
+    const bool mine = tid < kSlots;
+    double v[kSums];  // nf, snd, sd, ssc, nnz, taken, edges
+#pragma unroll
+    for (int f = 0; f < kSums; ++f) v[f] = mine ? p_own.sum[f] : 0.0;
+    double mrem_prev = mine ? __longlong_as_double((long long)p_own.mrem) : 0.0;
+    block_reduce_k<kRT, kSums>(v, mrem_prev, s_red);
     const double nf = v[0], snd = v[1], sd = v[2], ssc = v[3], nnz = v[4], taken = v[5],
                  edges = v[6];
     int reason = 0;
@@ -413,8 +418,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     // nothing, fall back to the largest untaken score (at least the mean,
     // so the Lemma of Section 3.1 keeps its progress guarantee).
     theta = nnz > 0 ? a.c * (ssc / nnz) * (nf > 0 ? R / nf : 0.0) : 0.0;
-    if (taken == 0 && theta > mrem) theta = mrem;
-    if (b == 0 && tid == 0) {
+    if (taken == 0 && theta > mrem_prev) theta = mrem_prev;
+    if (b == 0 && tid == 0 && !ended) {
       ctl->nodes_total += (long long)taken;
       ctl->edges_total += (long long)edges;
       ctl->last_taken = (long long)taken;
@@ -428,6 +433,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     }
   }
 
+  if (ended) return;
+
   // 2. Window fluid (fp64 in LDS) plus the pushes of round r-1.
 #pragma unroll
   for (int k = 0; k < kWinPer; ++k) {
@@ -438,10 +445,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   for (int q0 = tid + kWinPer * kRT; q0 < wn; q0 += kWinPer * kRT) {
     T fr[kWinPer];
 #pragma unroll
-    for (int k = 0; k < kWinPer; ++k) {
-      const int q = q0 + k * kRT;
-      fr[k] = q < wn ? Fv[j0 + q] : (T)0;
-    }
+    for (int k = 0; k < kWinPer; ++k) fr[k] = Fv[j0 + min(q0 + k * kRT, wn - 1)];
 #pragma unroll
     for (int k = 0; k < kWinPer; ++k) {
       const int q = q0 + k * kRT;
@@ -449,10 +453,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     }
   }
   if (tid < nb) {
-    s_pre[tid] = c_own;
+    s_pre[tid] = r >= 1 ? c_own : 0;
     if constexpr (!GT) {
-      s_soff[tid] = o_own;
-      s_base[tid] = base_own;
+      s_soff[tid] = r >= 1 ? o_own : 0;
+      s_base[tid] = bs_own + sT_own;
       s_cap[tid] = cap_own;
     }
   }
@@ -520,7 +524,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   PairT<T>* out = a.pairs[r & 1] + (int64_t)vb * a.mrec;
   const uint32_t wmask = (uint32_t)W - 1u;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // nf, snd, sd, ssc, nnz, taken, edges
-  mrem = 0.0;  // now: the largest untaken score of this window
+  double mrem = 0.0;  // the largest untaken score of this window
   // A. Decide for every node of the window (LDS only) before any push, so a
   //    round takes one set S (reading 5) even though pushes that stay inside
   //    the window are applied to its LDS copy at once.  Bit k of tbits: this
