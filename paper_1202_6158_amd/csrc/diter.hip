@@ -446,10 +446,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     T fr[kWinPer];
 #pragma unroll
     for (int k = 0; k < kWinPer; ++k) fr[k] = Fv[j0 + min(q0 + k * kRT, wn - 1)];
+    // W / kRT is then a multiple of kWinPer, so every q is inside the window;
+    // entries past wn are written as zeros (nothing reads them as fluid)
 #pragma unroll
     for (int k = 0; k < kWinPer; ++k) {
       const int q = q0 + k * kRT;
-      if (q < wn) win[q] = (double)fr[k];
+      win[q] = q < wn ? (double)fr[k] : 0.0;
     }
   }
   if (tid < nb) {
@@ -460,12 +462,31 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       s_cap[tid] = cap_own;
     }
   }
-  for (int s = tid + kRT; s < nb; s += kRT) {
-    s_pre[s] = r >= 1 ? cnt_in[s] : 0;
-    if constexpr (!GT) {
-      if (r >= 1) s_soff[s] = a.soff[(int64_t)b * nb + s];
-      s_base[s] = a.bstart[s] + a.soffT[(int64_t)b * nb + s];
-      s_cap[s] = a.capT[(int64_t)b * nb + s];
+  // the rest of the windows, two per thread at a time (loads first)
+  for (int s0 = tid + kRT; s0 < nb; s0 += 2 * kRT) {
+    int32_t c2[2], o2[2] = {0, 0}, t2[2] = {0, 0}, k2[2] = {0, 0};
+    int64_t b2[2] = {0, 0};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int sc = min(s0 + u * kRT, nb - 1);
+      c2[u] = cnt_in[sc];
+      if constexpr (!GT) {
+        o2[u] = a.soff[(int64_t)b * nb + sc];
+        b2[u] = a.bstart[sc];
+        t2[u] = a.soffT[(int64_t)b * nb + sc];
+        k2[u] = a.capT[(int64_t)b * nb + sc];
+      }
+    }
+    // (a clamped entry is written again with its own values: no branch)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int s = min(s0 + u * kRT, nb - 1);
+      s_pre[s] = r >= 1 ? c2[u] : 0;
+      if constexpr (!GT) {
+        s_soff[s] = r >= 1 ? o2[u] : 0;
+        s_base[s] = b2[u] + t2[u];
+        s_cap[s] = k2[u];
+      }
     }
   }
   __syncthreads();
