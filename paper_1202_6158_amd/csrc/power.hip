@@ -146,9 +146,14 @@ __global__ __launch_bounds__(kBlock) void k_pull(PowArgs<G> a, int k) {
         const int64_t e = e00 + (int64_t)q * kBlock;
         src[q] = e < e1 ? a.in_src[e] : -1;
       }
+      // unconditional gathers (a slot past the end reads entry 0), so that
+      // none waits for another: a load in a branch gets a wait of its own
+      G g[kGU];
+#pragma unroll
+      for (int q = 0; q < kGU; ++q) g[q] = xs[max(src[q], 0)];
       double t[kGU];
 #pragma unroll
-      for (int q = 0; q < kGU; ++q) t[q] = src[q] >= 0 ? (double)xs[src[q]] : 0.0;
+      for (int q = 0; q < kGU; ++q) t[q] = src[q] >= 0 ? (double)g[q] : 0.0;
 #pragma unroll
       for (int q = 0; q < kGU; ++q) {
         const int64_t e = e00 + (int64_t)q * kBlock;
@@ -173,9 +178,12 @@ __global__ __launch_bounds__(kBlock) void k_pull(PowArgs<G> a, int k) {
         const int64_t e = e00 + (int64_t)q * kBlock;
         src[q] = e < e1 ? a.in_src[e] : -1;
       }
+      G g[kGB];  // unconditional gathers, as above
+#pragma unroll
+      for (int q = 0; q < kGB; ++q) g[q] = xs[max(src[q], 0)];
       double t[kGB];
 #pragma unroll
-      for (int q = 0; q < kGB; ++q) t[q] = src[q] >= 0 ? (double)xs[src[q]] : 0.0;
+      for (int q = 0; q < kGB; ++q) t[q] = src[q] >= 0 ? (double)g[q] : 0.0;
 #pragma unroll
       for (int q = 0; q < kGB; ++q) {
         const int64_t e = e00 + (int64_t)q * kBlock;
