@@ -594,17 +594,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         acc[0] = NAN;
       }
       s_state[q] = st;
-      tbits |= (uint32_t)st << (k0 + u);
-      const unsigned long long m = __ballot(st != 0);
-      if ((tid & 63) == 0) s_chunk[q >> 6] = __popcll(m);
+      if (W > kSuper) {  // uniform: a list can save passes only then
+        tbits |= (uint32_t)st << (k0 + u);
+        const unsigned long long m = __ballot(st != 0);
+        if ((tid & 63) == 0) s_chunk[q >> 6] = __popcll(m);
+      }
     }
   }
   __syncthreads();
   // When the list can hold them, list the taken nodes in node order (chunk
   // offsets plus the rank within the chunk) and run the passes over the list;
   // otherwise every pass walks kSuper consecutive nodes.
-  const long long ntk = lds_exscan<kRT>(s_chunk, W >> 6, s_scr);
-  const bool use_list = ntk <= list_cap;
+  // (a window of at most kSuper nodes is one pass either way: no list)
+  const long long ntk = W > kSuper ? lds_exscan<kRT>(s_chunk, W >> 6, s_scr) : 0;
+  const bool use_list = W > kSuper && ntk <= list_cap;
   if (use_list && ntk > 0) {
     for (int q = tid, k = 0; q < W; q += kRT, ++k) {
       const bool t = (tbits >> k) & 1u;
