@@ -446,8 +446,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     T fr[kWinPer];
 #pragma unroll
     for (int k = 0; k < kWinPer; ++k) fr[k] = Fv[j0 + min(q0 + k * kRT, wn - 1)];
-    // W / kRT is then a multiple of kWinPer, so every q is inside the window;
-    // entries past wn are written as zeros (nothing reads them as fluid)
+    // (this loop runs only when W > kWinPer * kRT: W / kRT is then a power
+    // of two of at least 8, a multiple of kWinPer, so every q is inside the
+    // window; entries past wn are written as zeros, read by nothing as fluid)
 #pragma unroll
     for (int k = 0; k < kWinPer; ++k) {
       const int q = q0 + k * kRT;

@@ -214,9 +214,4 @@ __device__ __forceinline__ void block_exscan2(long long a, long long b, long lon
   *tb = sb;
 }
 
-template <typename T>
-__device__ __forceinline__ T ld_relaxed(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 }  // namespace di
