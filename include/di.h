@@ -103,7 +103,14 @@ typedef struct di_tune {
   int32_t tables;      /* per-window segment tables of the binned scatter: 0 = in LDS when they
                           fit, else in global memory (graphs above ~25M nodes); 1 = LDS only;
                           2 = global memory (runs 1024-thread workgroups) */
+  int32_t persist;     /* di_solve only: 1 = one cooperative launch runs every round, each
+                          window's fluid, history, degrees and (when they fit) out-links held
+                          in its workgroup's LDS for the whole solve, rounds separated by a grid
+                          barrier; graphs of at most DI_PERSIST_MAX_WINDOWS windows of at most
+                          2^11 nodes (DI_EINVAL otherwise).  Same rounds, thresholds and stop as
+                          the launch-per-round path.  0 = one launch per round. */
 } di_tune;
+#define DI_PERSIST_MAX_WINDOWS 128
 
 typedef struct di_opts {
   double d;           /* damping factor, 0 <= d < 1 */
@@ -312,7 +319,10 @@ typedef struct di_tune_trial {
  * each direction while the time improves, then the three fastest pairs of
  * the first step at the chosen window with 1024-thread workgroups; for
  * DI_TUNE_SOLVE on a graph of at most DI_SMALL_MAX_NODES
- * nodes, also every schedule x c in the whole-graph window (DI_WINDOW_WHOLE).
+ * nodes, also every schedule x c in the whole-graph window (DI_WINDOW_WHOLE);
+ * and for DI_TUNE_SOLVE on a graph that the one-launch solve takes
+ * (di_tune.persist), every schedule x c at the smallest window it allows,
+ * then the best pair at larger windows while the time improves.
  * Any schedule converges to the same limit (the order
  * independence of Sections 2.2 and 3.1), so only speed is compared.
  * The default knobs (mean, c = 1) run first; every other candidate gets at

@@ -81,13 +81,14 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
 
     std::vector<Trial> done;
     di_opts cand_opts = *opts;
-    auto run = [&](int sched, float c, int wlog, int threads = 0) {
+    auto run = [&](int sched, float c, int wlog, int threads = 0, int persist = 0) {
       di_tune t{};
       t.schedule = sched;
       t.c = c;
       t.window_log2 = wlog;
       t.check_every = 0;
       t.threads = threads;
+      t.persist = persist;
       done.push_back(run_candidate(g, mode, cand_opts, B, seed_ptr, seeds, t, s));
       return done.back();
     };
@@ -150,6 +151,30 @@ extern "C" di_status di_autotune(di_graph* g, int32_t mode, const di_opts* opts,
           const Trial t = run(sc, c, DI_WINDOW_WHOLE);
           if (better(t, win)) win = t;
         }
+    }
+    // 5. single solves on graphs of at most DI_PERSIST_MAX_WINDOWS windows:
+    //    one launch for every round, at every schedule x threshold factor at
+    //    the smallest window that allows it, then larger windows for the
+    //    best pair while the time improves
+    if (mode == DI_TUNE_SOLVE) {
+      int wp = w0;
+      while (wp <= 11 && !persist_fits(g->n, g->m, wp)) ++wp;
+      if (wp <= 11) {
+        Trial pbest{};
+        pbest.status = DI_EINVAL;
+        for (int sc : scheds)
+          for (float c : cs) {
+            const Trial t = run(sc, c, wp, 0, 1);
+            if (better(t, pbest)) pbest = t;
+          }
+        for (int wl = wp + 1; pbest.status == DI_OK && wl <= 11 && persist_fits(g->n, g->m, wl);
+             ++wl) {
+          const Trial t = run(pbest.tune.schedule, pbest.tune.c, wl, 0, 1);
+          if (!better(t, pbest)) break;
+          pbest = t;
+        }
+        if (better(pbest, win)) win = pbest;
+      }
     }
     const int nt = (int)done.size();
     for (int k = 0; k < nt && k < max_trials; ++k) {

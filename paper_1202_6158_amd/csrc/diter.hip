@@ -193,6 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DiArgs<T> a, const double* __re
     c->stop_round = -1;
     c->reason = 0;
     c->err = 0;
+    c->bar = 0;
     c->nf = 0.0;
     c->theta = a.theta0;
     c->nodes_total = c->edges_total = 0;
@@ -252,7 +253,8 @@ __global__ __launch_bounds__(kBlock) void k_resume_scores(DiArgs<T> a, double* _
 }
 
 // In-place exclusive scan of arr[0..n) in LDS (NT threads); returns the total.
-template <int NT>
+// L: LDS-only barriers (see wg_barrier).
+template <int NT, bool L = false>
 __device__ long long lds_exscan(int32_t* arr, int n, long long* scr) {
   const int per = (n + NT - 1) / NT;
   const int s0 = threadIdx.x * per;
@@ -260,14 +262,14 @@ __device__ long long lds_exscan(int32_t* arr, int n, long long* scr) {
   for (int k = 0; k < per; ++k)
     if (s0 + k < n) loc += arr[s0 + k];
   long long tot = 0;
-  long long run = block_exscan<NT>(loc, scr, &tot);
+  long long run = block_exscan<NT, L>(loc, scr, &tot);
   for (int k = 0; k < per; ++k)
     if (s0 + k < n) {
       const int32_t v = arr[s0 + k];
       arr[s0 + k] = (int32_t)run;
       run += v;
     }
-  __syncthreads();
+  wg_barrier<L>();
   return tot;
 }
 
@@ -1459,6 +1461,487 @@ static void launch_small(const DiArgs<T>& a, Workspace* ws, int sched, hipStream
   else go(k_small<T, DI_SCHED_MEAN>);
 }
 
+// ------------------------------------------- one launch for every round
+
+// Graphs of at most kResMaxWindows windows: one cooperative launch runs every
+// round of a single solve.  The workgroup of a window keeps the window's
+// fluid and history (fp64), degrees, link offsets and, when they fit, its
+// out-links in LDS for the whole solve; only what crosses windows goes
+// through global memory: the records of cross-window pushes, their counts
+// and the round sums.  Rounds are separated by a grid barrier instead of
+// launches.  Round r computes what launch r of k_round computes (the same
+// threshold and stop from the same sums, the same records and counts), so a
+// round diffuses one set S (reading 5) and the stop is the fresh fp64
+// ||F||_1 < tol of Theorem 2; in fp32 the fluid is rounded to fp32 at the end
+// of each round, as a stored F would be.
+constexpr int kResThreads = 256;
+constexpr int kResMaxWindows = DI_PERSIST_MAX_WINDOWS;
+constexpr int kResMaxWlog = 11;
+constexpr int kResPass = 2 * kResThreads;  // taken nodes expanded per pass
+constexpr int kResLinkCap = 24576;         // out-links of a window held in LDS, at most
+constexpr int kResSpec = 4;                // speculative record reads per thread per round
+
+// Grid barrier of co-resident workgroups: an arrival counter that grows by
+// the number of workgroups every round (target = rounds so far x workgroups).
+// A wait longer than `limit` ticks of the constant-rate wall clock, or an
+// abort seen while waiting, sets bit 4 of *err and returns false: every
+// workgroup then leaves its loop at this or its next barrier.
+__device__ bool grid_barrier(unsigned* bar, unsigned target, int* err, long long limit,
+                             int* s_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long t0 = wall_clock64();
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if ((__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4) ||
+          wall_clock64() - t0 > limit) {
+        __hip_atomic_fetch_or(err, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_flag = ok;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+// LDS bytes of k_resident for 2^wlog-node windows, nb windows and link_cap
+// cached out-links: fluid and history (8 B per node), link offsets, degrees,
+// in-degrees (4 B each), taken list (2 B), state (1 B); per window 8 B record
+// base, 4 B fold offset, 4 B capacity, 4 B counter, 4 B speculative-read
+// prefix, 4 B received count.
+static size_t res_lds_bytes(int wlog, int nb, int link_cap) {
+  const size_t W = (size_t)1 << wlog;
+  return 16 * W + 8 * (size_t)nb + 4 * (W + 1) + 8 * W + 8 * ((size_t)nb + 1) + 16 * (size_t)nb +
+         2 * W + W + 4 * (size_t)link_cap;
+}
+
+template <typename T, int SCHED>
+__global__ __launch_bounds__(kResThreads) void k_resident(DiArgs<T> a, int link_cap,
+                                                          long long spin_limit) {
+  constexpr int NT = kResThreads;
+  constexpr int kNPT = kResPass / NT;
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int W = 1 << a.wlog;
+  const int nb = a.nb;
+  const double d = a.d, tol = a.tol;
+  Ctl* const ctl = a.ctl;
+  Slot* const slots = a.slots;
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* const win = reinterpret_cast<double*>(smem);      // [W] fluid
+  double* const hist = win + W;                              // [W] history
+  int64_t* const s_base = reinterpret_cast<int64_t*>(hist + W);  // [nb] record base per destination
+  int32_t* const s_row = reinterpret_cast<int32_t*>(s_base + nb);  // [W+1] link offsets
+  int32_t* const s_deg = s_row + W + 1;                      // [W]
+  int32_t* const s_in = s_deg + W;                           // [W] (ALGO-OP)
+  int32_t* const s_pre = s_in + W;                           // [nb+1] fold prefix, then ranks
+  int32_t* const s_soff = s_pre + nb + 1;                    // [nb] fold offset per source
+  int32_t* const s_cap = s_soff + nb;                        // [nb] capacity per destination
+  int32_t* const s_kin = s_cap + nb;                         // [nb+1] speculative records per source
+  int32_t* const s_cnt = s_kin + nb + 1;                     // [nb] records received per source
+  uint16_t* const s_list = reinterpret_cast<uint16_t*>(s_cnt + nb);  // [W] taken list
+  uint8_t* const s_state = reinterpret_cast<uint8_t*>(s_list + W);   // [W]
+  int32_t* const s_col = reinterpret_cast<int32_t*>(s_state + W);    // [link_cap]
+  __shared__ int32_t s_beo[kResPass + 1];
+  __shared__ int32_t s_brow[kResPass];
+  __shared__ double s_bsh[kResPass];
+  __shared__ int32_t s_chunk[(1 << kResMaxWlog) / 64];
+  __shared__ double s_red[block_reduce_k_scratch<NT, kSums>()];
+  __shared__ long long s_scr[2 * (NT / 64)];
+  __shared__ int s_flag;
+  __shared__ int s_any, s_lp;  // records arrived this round; a push stayed in the window
+
+  // The window, once.
+  const int64_t j0 = (int64_t)b << a.wlog;
+  const int wn = (int)min((int64_t)W, a.n - j0);
+  const int64_t e0 = a.row_ptr[j0];
+  const int nlinks = (int)(a.row_ptr[j0 + wn] - e0);
+  const bool lcache = nlinks <= link_cap;
+  for (int q = tid; q < W; q += NT) {
+    const bool in = q < wn;
+    const int64_t j = j0 + min(q, wn - 1);
+    win[q] = in ? (double)a.F[j] : 0.0;
+    hist[q] = in ? a.H[j] : 0.0;
+    s_deg[q] = in ? a.deg[j] : 0;
+    s_in[q] = in && SCHED == DI_SCHED_OP ? a.indeg[j] : 0;
+    s_row[q] = in ? (int)(a.row_ptr[j] - e0) : nlinks;
+  }
+  if (tid == 0) s_row[W] = nlinks;
+  if (lcache)
+    for (int e = tid; e < nlinks; e += NT) s_col[e] = a.col[e0 + e];
+  for (int w = tid; w < nb; w += NT) {
+    s_soff[w] = a.soff[(int64_t)b * nb + w];
+    s_base[w] = a.bstart[w] + a.soffT[(int64_t)b * nb + w];
+    s_cap[w] = a.capT[(int64_t)b * nb + w];
+  }
+  // Records sent to this window are read speculatively: the first K of each
+  // incoming segment (an equal share of kResSpec per thread) are loaded with
+  // the round's counts, in one wait, and those past the count dropped; only
+  // a segment that received more than K needs a second, dependent read.
+  const int capin = tid < nb ? a.capT[(int64_t)tid * nb + b] : 0;  // links from window tid here
+  const int nsrc = __syncthreads_count(capin > 0);
+  const int K = nsrc > 0 ? kResSpec * NT / nsrc : 0;
+  if (tid < nb) s_kin[tid] = min(capin, K);
+  __syncthreads();
+  const int spec_total = (int)lds_exscan<NT>(s_kin, nb, s_scr);
+  if (tid == 0) s_kin[nb] = spec_total;
+  __syncthreads();
+  int sp_off[kResSpec], sp_src[kResSpec], sp_i[kResSpec];  // record offset, source, index in segment
+#pragma unroll
+  for (int u = 0; u < kResSpec; ++u) {
+    const int slot = tid + u * NT;
+    sp_src[u] = 0;
+    sp_i[u] = INT_MAX;  // never below a count: an unused slot (its read is clamped and dropped)
+    sp_off[u] = 0;
+    if (slot < spec_total) {
+      const int s = upper_idx(s_kin, nb, slot);
+      sp_src[u] = s;
+      sp_i[u] = slot - s_kin[s];
+      sp_off[u] = s_soff[s] + sp_i[u];
+    }
+  }
+  const int64_t rbase = a.bstart[b];  // first record of this window's region
+  int active = a.active[b];
+  const uint32_t wmask = (uint32_t)W - 1u;
+  if (tid == 0) s_any = s_lp = 0;
+  __syncthreads();
+
+  for (int r = 0;; ++r) {
+    // Round r-1's sums and the counts of the records it sent to this window
+    // (clamped indices, no branch: one wait covers both).
+    const Slot* P = slots + ((r + 2) % 3) * kSlots;
+    const Slot p_own = P[min(tid, kSlots - 1)];
+    int32_t* const cnt_in = a.cnt[(r - 1) & 1] + (int64_t)b * nb;
+    const int32_t c_own = cnt_in[min(tid, nb - 1)];
+    const PairT<T>* const pr = a.pairs[(r - 1) & 1];
+    PairT<T> sp[kResSpec];
+#pragma unroll
+    for (int u = 0; u < kResSpec; ++u) sp[u] = pr[min(rbase + sp_off[u], a.mrec - 1)];
+
+    // 1. Decisions from round r-1's sums (identical in every workgroup).
+    double theta = a.theta0;
+    bool stop = false;
+    if (r >= 1) {
+      if (b == 0 && tid < kSlots) {  // set (r+1) % 3 is next written in round r+1
+        Slot* z = slots + ((r + 1) % 3) * kSlots + tid;
+#pragma unroll
+        for (int f = 0; f < kSums; ++f) z->sum[f] = 0.0;
+        z->mrem = 0;
+      }
+      const bool mine = tid < kSlots;
+      double v[kSums];  // nf, snd, sd, ssc, nnz, taken, edges
+#pragma unroll
+      for (int f = 0; f < kSums; ++f) v[f] = mine ? p_own.sum[f] : 0.0;
+      double mrem_prev = mine ? __longlong_as_double((long long)p_own.mrem) : 0.0;
+      block_reduce_k<NT, kSums, true>(v, mrem_prev, s_red);
+      const double nf = v[0], snd = v[1], sd = v[2], ssc = v[3], nnz = v[4], taken = v[5],
+                   edges = v[6];
+      int reason = 0;
+      if (!isfinite(nf)) reason = 2;
+      else if (nf < tol) reason = 1;
+      else if ((int64_t)r >= a.max_rounds) reason = 3;
+      stop = reason != 0;
+      const double R = nf - (1.0 - d) * snd - sd;
+      theta = nnz > 0 ? a.c * (ssc / nnz) * (nf > 0 ? R / nf : 0.0) : 0.0;
+      if (taken == 0 && theta > mrem_prev) theta = mrem_prev;
+      if (b == 0 && tid == 0) {
+        ctl->nodes_total += (long long)taken;
+        ctl->edges_total += (long long)edges;
+        ctl->last_taken = (long long)taken;
+        ctl->last_edges = (long long)edges;
+        ctl->theta = theta;
+        ctl->nf = nf;
+        if (stop) {
+          ctl->reason = reason;
+          ctl->stop_round = r - 1;
+        }
+      }
+    }
+
+    // 2. The pushes of round r-1 into this window: the speculative reads,
+    //    then whatever a segment received beyond them.
+    if (tid < nb) {
+      const int c = r >= 1 ? c_own : 0;
+      s_cnt[tid] = c;
+      s_pre[tid] = max(c - (s_kin[tid + 1] - s_kin[tid]), 0);
+      if (c > 0) s_any = 1;
+    }
+    wg_barrier<true>();
+    const bool received = s_any != 0;
+#pragma unroll
+    for (int u = 0; u < kResSpec; ++u)
+      if (sp_i[u] < s_cnt[sp_src[u]] && sp[u].loc < (uint32_t)wn)
+        atomicAdd(&win[sp[u].loc], (double)sp[u].val);
+    const long long rest = r >= 1 ? lds_exscan<NT, true>(s_pre, nb, s_scr) : 0;
+    if (rest > 0) {
+      const long long total = rest;
+      for (long long i0 = (long long)tid * kRun; i0 < total; i0 += (long long)NT * kRun) {
+        int s = upper_idx(s_pre, nb, i0);
+        long long nxt = s + 1 < nb ? s_pre[s + 1] : total;
+        int64_t sb = rbase + s_soff[s] + (s_kin[s + 1] - s_kin[s]) - s_pre[s];
+        int64_t idx[kRun];
+#pragma unroll
+        for (int u = 0; u < kRun; ++u) {
+          const long long i = i0 + u;
+          idx[u] = -1;
+          if (i < total) {
+            while (i >= nxt) {
+              ++s;
+              nxt = s + 1 < nb ? s_pre[s + 1] : total;
+              sb = rbase + s_soff[s] + (s_kin[s + 1] - s_kin[s]) - s_pre[s];
+            }
+            idx[u] = sb + i;
+          }
+        }
+        PairT<T> e[kRun];
+#pragma unroll
+        for (int u = 0; u < kRun; ++u)
+          if (idx[u] >= 0) e[u] = pr[idx[u]];
+#pragma unroll
+        for (int u = 0; u < kRun; ++u)
+          if (idx[u] >= 0 && e[u].loc < (uint32_t)wn) atomicAdd(&win[e[u].loc], (double)e[u].val);
+      }
+    }
+    // consumed: cleared for round r+1, which writes this row again
+    if (r >= 1 && tid < nb && c_own != 0) cnt_in[tid] = 0;
+    wg_barrier<true>();
+    if (stop) break;  // uniform: every workgroup reads the same sums
+
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // nf, snd, sd, ssc, nnz, taken, edges
+    double mrem = 0.0;
+    if (received || active) {  // uniform
+      // 3. Decide for every node of the window (LDS only), then list the
+      //    taken nodes in node order (per 64-node chunk: offset plus rank).
+      uint32_t tbits = 0;
+      for (int q = tid, k = 0; q < W; q += NT, ++k) {
+        const double f = q < wn ? win[q] : 0.0, af = fabs(f);
+        uint8_t st = 0;
+        if (af > 0.0) {
+          acc[0] += af;
+          acc[4] += 1.0;
+          const double sc = node_score<SCHED>(af, s_deg[q], s_in[q]);
+          acc[3] += sc;
+          if (sc >= theta) st = 1;
+          else mrem = fmax(mrem, sc);
+        } else if (f != f) {
+          acc[0] = NAN;
+        }
+        s_state[q] = st;
+        tbits |= (uint32_t)st << k;
+        const unsigned long long m = __ballot(st != 0);
+        if ((tid & 63) == 0) s_chunk[q >> 6] = __popcll(m);
+      }
+      wg_barrier<true>();
+      const int ntk = (int)lds_exscan<NT, true>(s_chunk, W >> 6, s_scr);
+      if (ntk > 0) {
+        for (int q = tid, k = 0; q < W; q += NT, ++k) {
+          const bool t = (tbits >> k) & 1u;
+          const unsigned long long m = __ballot(t);
+          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+          if (t) s_list[s_chunk[q >> 6] + rank] = (uint16_t)q;
+        }
+      }
+      for (int w = tid; w < nb; w += NT) s_pre[w] = 0;  // now: records written per destination
+      wg_barrier<true>();
+      int32_t* const cnt_out = a.cnt[r & 1];
+      PairT<T>* const out = a.pairs[r & 1];
+      for (int t0 = 0; t0 < ntk; t0 += kResPass) {
+        // 4. Take the pass's nodes (H_i += F_i, F_i = 0) and stage the
+        //    pushing ones with their link offsets and shares.
+        long long npush = 0, nedge = 0;
+        int qs[kNPT];
+        double f[kNPT];
+#pragma unroll
+        for (int u = 0; u < kNPT; ++u) {
+          const int i = t0 + tid + u * NT;
+          qs[u] = -1;
+          f[u] = 0.0;
+          if (i >= ntk) continue;
+          const int q = s_list[i];
+          qs[u] = q;
+          f[u] = win[q];
+          hist[q] += f[u];
+          win[q] = 0.0;
+          s_state[q] = 2;
+          if (a.trace && r < a.trace_rounds) a.trace[(int64_t)r * a.n + j0 + q] = 1;
+          acc[5] += 1.0;
+          const int dg = s_deg[q];
+          if (dg > 0) {
+            acc[1] += fabs(f[u]);
+            ++npush;
+            nedge += dg;
+          } else {
+            acc[2] += fabs(f[u]);
+          }
+        }
+        long long slot = 0, eoff = 0, ntile = 0, etile = 0;
+        block_exscan2<NT, true>(npush, nedge, s_scr, &slot, &eoff, &ntile, &etile);
+        if (ntile == 0) continue;  // uniform
+#pragma unroll
+        for (int u = 0; u < kNPT; ++u) {
+          if (qs[u] < 0 || s_deg[qs[u]] == 0) continue;
+          const int dg = s_deg[qs[u]];
+          s_beo[slot] = (int32_t)eoff;
+          s_brow[slot] = s_row[qs[u]];
+          s_bsh[slot] = a.weighted ? d * f[u] : d * f[u] / (double)dg;
+          ++slot;
+          eoff += dg;
+        }
+        wg_barrier<true>();
+        // 5. Push every staged link (kRun consecutive links per thread): into
+        //    the LDS fluid when the target is in this window and not a node
+        //    of S still to be expanded, else as a record.
+        const int bcount = (int)ntile;
+        for (long long t00 = (long long)tid * kRun; t00 < etile; t00 += (long long)NT * kRun) {
+          int k = upper_idx(s_beo, bcount, t00);
+          long long nxt = k + 1 < bcount ? s_beo[k + 1] : etile;
+          int lb = s_brow[k] - s_beo[k];  // window link index = lb + t for node k
+          double sh = s_bsh[k];
+          int e[kRun];
+          double v[kRun];
+#pragma unroll
+          for (int u = 0; u < kRun; ++u) {
+            const long long t = t00 + u;
+            e[u] = -1;
+            v[u] = 0.0;
+            if (t < etile) {
+              while (t >= nxt) {
+                ++k;
+                nxt = k + 1 < bcount ? s_beo[k + 1] : etile;
+                lb = s_brow[k] - s_beo[k];
+                sh = s_bsh[k];
+              }
+              e[u] = lb + (int)t;
+              v[u] = sh;
+            }
+          }
+          uint32_t dst[kRun];
+#pragma unroll
+          for (int u = 0; u < kRun; ++u)
+            if (e[u] >= 0) {
+              dst[u] = (uint32_t)(lcache ? s_col[e[u]] : a.col[e0 + e[u]]);
+              if (a.weighted) v[u] *= a.w[e0 + e[u]];
+            }
+#pragma unroll
+          for (int u = 0; u < kRun; ++u) {
+            if (e[u] < 0) continue;
+            const int w = (int)(dst[u] >> a.wlog);
+            if (w == b && s_state[dst[u] & wmask] != 1) {
+              atomicAdd(&win[dst[u] & wmask], (double)(T)v[u]);
+              s_lp = 1;
+              continue;
+            }
+            const int rank = atomicAdd(&s_pre[w], 1);
+            if (rank < s_cap[w]) {
+              PairT<T> pr;
+              memset(&pr, 0, sizeof(pr));
+              pr.loc = dst[u] & wmask;
+              pr.val = (T)v[u];
+              out[s_base[w] + rank] = pr;
+            } else {
+              atomicOr(&ctl->err, 2);
+            }
+          }
+        }
+        acc[6] += (double)etile;  // uniform: counted once below (thread 0 only)
+        wg_barrier<true>();
+      }
+      for (int w = tid; w < nb; w += NT)
+        if (s_pre[w] > 0) cnt_out[(int64_t)w * nb + b] = min(s_pre[w], s_cap[w]);
+      if constexpr (std::is_same<T, float>::value)
+        for (int q = tid; q < wn; q += NT) win[q] = (double)(float)win[q];
+    }
+
+    // 6. This window's sums, added into its slot; then wait for every window.
+    const int local_any = s_lp;  // after the last pass's barrier
+    const double edges = acc[6];
+    acc[6] = 0.0;
+    block_reduce_k<NT, kSums, true>(acc, mrem, s_red);
+    active = (acc[4] > acc[5] || local_any) ? 1 : 0;
+    if (tid == 0) {
+      s_any = s_lp = 0;  // every thread read both before the reduction's barriers
+      acc[6] = edges;
+      Slot* sl = slots + (r % 3) * kSlots + (b % kSlots);
+#pragma unroll
+      for (int f = 0; f < kSums; ++f)
+        if (acc[f] != 0.0) unsafeAtomicAdd(&sl->sum[f], acc[f]);
+      if (mrem > 0.0) atomicMax(&sl->mrem, (unsigned long long)__double_as_longlong(mrem));
+    }
+    if (!grid_barrier(&ctl->bar, (unsigned)(r + 1) * (unsigned)nb,
+                      &ctl->err, spin_limit, &s_flag))
+      break;
+  }
+  for (int q = tid; q < wn; q += NT) {
+    a.F[j0 + q] = (T)win[q];
+    a.H[j0 + q] = hist[q];
+  }
+  if (tid == 0) a.active[b] = active;
+}
+
+// Whether a single solve at 2^wlog-node windows can run as one launch.
+static bool resident_fits(int64_t n, int64_t m, int wlog, bool gt) {
+  const int64_t nb = (n + (1ll << wlog) - 1) >> wlog;
+  return !gt && wlog <= kResMaxWlog && nb <= kResMaxWindows && m < (1ll << 31) &&
+         res_lds_bytes(wlog, (int)nb, 0) <= 120 * 1024;
+}
+
+bool persist_fits(int64_t n, int64_t m, int wlog) { return resident_fits(n, m, wlog, false); }
+
+template <typename T>
+static void launch_resident(const DiArgs<T>& a, int sched, hipStream_t s, LaunchTimer* lt) {
+  DI_REQUIRE(a.nvec == 1 && a.nb <= kResMaxWindows && a.wlog <= kResMaxWlog,
+             "the one-launch solve needs at most 128 windows of at most 2^11 nodes");
+  // dynamic LDS limit of the three instances (set once) and the wall-clock rate
+  static const size_t dyn_limit = [] {
+    size_t lim = ~(size_t)0;
+    auto one = [&](const void* k) {
+      hipFuncAttributes fa;
+      DI_HIP(hipFuncGetAttributes(&fa, k));
+      int dev = 0, mx = 0;
+      DI_HIP(hipGetDevice(&dev));
+      DI_HIP(hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      const size_t dl = (size_t)mx - fa.sharedSizeBytes;
+      DI_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl));
+      lim = std::min(lim, dl);
+    };
+    one((const void*)k_resident<T, DI_SCHED_MEAN>);
+    one((const void*)k_resident<T, DI_SCHED_OP2>);
+    one((const void*)k_resident<T, DI_SCHED_OP>);
+    return lim;
+  }();
+  static const long long ticks_per_s = [] {
+    int dev = 0, khz = 0;
+    DI_HIP(hipGetDevice(&dev));
+    DI_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    return (long long)std::max(khz, 1) * 1000;
+  }();
+  const size_t base = res_lds_bytes(a.wlog, a.nb, 0);
+  DI_REQUIRE(base <= dyn_limit, "window too large for the one-launch solve");
+  int link_cap = (int)std::min<size_t>((dyn_limit - base) / 4, (size_t)kResLinkCap);
+  const size_t smem = res_lds_bytes(a.wlog, a.nb, link_cap);
+  long long limit = 2 * ticks_per_s;  // a barrier wait of 2 s means a fault, not a slow round
+  DiArgs<T> args = a;
+  void* params[] = {(void*)&args, (void*)&link_cap, (void*)&limit};
+  const void* kern = sched == DI_SCHED_OP2  ? (const void*)k_resident<T, DI_SCHED_OP2>
+                     : sched == DI_SCHED_OP ? (const void*)k_resident<T, DI_SCHED_OP>
+                                            : (const void*)k_resident<T, DI_SCHED_MEAN>;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (lt && lt->on) {
+    lt->next(&e0, &e1);
+    DI_HIP(hipEventRecord(e0, s));
+  }
+  DI_HIP(hipLaunchCooperativeKernel(kern, dim3(a.nb), dim3(kResThreads), params, (unsigned)smem, s));
+  if (e1) DI_HIP(hipEventRecord(e1, s));
+}
+
 // Zero the flush slots of the vectors of this launch (slot vmap[blockIdx.x]).
 template <typename T>
 __global__ void k_zero_flush(DiArgs<T> a) {
@@ -1497,6 +1980,10 @@ static void fill_stats(const Ctl& h, const di_opts* o, double secs, di_stats* st
 }
 
 static di_status status_of(const Ctl& h) {
+  if (h.err & 4) {
+    set_error("grid barrier of the one-launch solve timed out");
+    return DI_EDEVICE;
+  }
   if (h.err) {
     set_error("internal segment consistency check failed (code " + std::to_string(h.err) + ")");
     return DI_EDEVICE;
@@ -1515,7 +2002,8 @@ static di_status status_of(const Ctl& h) {
 struct TuneParams {
   int sched, wlog, check_every, threads;
   bool gt;
-  bool whole;  // single solves: the whole graph in one workgroup's LDS (k_small)
+  bool whole;    // single solves: the whole graph in one workgroup's LDS (k_small)
+  bool persist;  // single solves: one launch for every round (k_resident)
   double c;
 };
 
@@ -1551,6 +2039,16 @@ static TuneParams tune_params(Graph* g, const di_tune* tn, int mode, int precisi
   p.threads = tn && tn->threads ? tn->threads : kRoundThreads;
   DI_REQUIRE(p.threads == 512 || p.threads == 1024, "threads must be 0, 512 or 1024");
   if (p.gt) p.threads = 1024;  // the only instance with tables in global memory
+  p.persist = mode == DI_TUNE_SOLVE && tn && tn->persist;
+  if (p.persist) {
+    DI_REQUIRE(tn->persist == 1 && !p.whole, "persist must be 0 or 1 (not with DI_WINDOW_WHOLE)");
+    // no window asked for: the smallest that allows it
+    if (tn->window_log2 == 0)
+      for (int k = p.wlog + 1; k <= kResMaxWlog && !resident_fits(g->n, g->m, p.wlog, p.gt); ++k)
+        p.wlog = window_log2_for(g->n, k, tables, &p.gt);
+    DI_REQUIRE(resident_fits(g->n, g->m, p.wlog, p.gt),
+               "persist needs at most 128 windows of at most 2^11 nodes and fewer than 2^31 links");
+  }
   return p;
 }
 
@@ -1607,6 +2105,7 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   k_init<T><<<dim3(grid_for(g->n, 2048), 1), kBlock, 0, s>>>(a, vdev, resume ? 1 : 0, 0);
   DI_HIP(hipGetLastError());
   if (tp.whole) launch_small(a, ws, tp.sched, s, &lt);
+  else if (tp.persist) launch_resident(a, tp.sched, s, &lt);
   else run_rounds(a, ws, tp.sched, tp.check_every, s, &lt);
   double* xo = x ? (dev ? x : ws->x.as<double>()) : nullptr;
   flush(a, xo, o->normalize, s);
@@ -1617,8 +2116,8 @@ static di_status solve_impl(Graph* g, const double* v, const di_opts* o, double*
   if (st) {
     fill_stats(*h, o, secs, st);
     // launches 0..stop_round take and expand; launch stop_round+1 folds (the
-    // whole-graph window: one launch).
-    const size_t working = tp.whole ? 1 : (size_t)h->stop_round + 2;
+    // whole-graph window and the one-launch solve: one launch).
+    const size_t working = tp.whole || tp.persist ? 1 : (size_t)h->stop_round + 2;
     st->kernel_seconds = lt.on ? lt.total(working) : 0.0;
     st->kernel_launches = lt.on ? (int64_t)working : 0;
   }

@@ -150,6 +150,9 @@ struct Graph {
 int window_log2_for(int64_t n, int requested, int tables, bool* global_tables);
 // LDS bytes of the round kernel's dynamic part for window 2^wlog and nb windows.
 size_t round_lds_bytes(int wlog, int nb, bool global_tables);
+// Whether a single solve of an n-node, m-link graph at 2^wlog-node windows
+// (LDS tables) can run every round in one launch (di_tune.persist).
+bool persist_fits(int64_t n, int64_t m, int wlog);
 
 // Workspaces (defined in diter.hip).
 Workspace* acquire_workspace(Graph* g, int precision, int wlog, bool global_tables);

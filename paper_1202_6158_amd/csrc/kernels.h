@@ -42,13 +42,13 @@ constexpr int kFlushSums = 5;       // sums the flush takes per vector
 constexpr int kFlushSlots = 256;    // partial-sum slots per flush sum
 constexpr int kFlushAcc = kFlushSums * kFlushSlots;
 
-// Control block in device memory.  Each field is written by workgroup 0 of
-// one launch and read only by later launches.
+// Control block in device memory.  Each field but bar is written by
+// workgroup 0 of one launch (one round) and read only by later ones.
 struct Ctl {
   int stop_round;  // -1 while running; else the last round whose set was taken
   int reason;      // 1 converged, 2 non-finite residual, 3 max rounds
-  int err;         // capacity / range violation (never set on valid input)
-  int pad;
+  int err;         // capacity / range violation (never set on valid input); 4: barrier time-out
+  unsigned bar;    // grid barrier arrivals of the one-launch solve
   double nf;       // ||F||_1 seen by the stopping round, before its take
   double theta;    // threshold of the latest round
   long long nodes_total, edges_total;  // diffusions and out-links used
@@ -56,6 +56,20 @@ struct Ctl {
   // flush sums: sum(H+F), sum(H), sum|F|, sum over dangling of H, sum(F)
   double fl[kFlushSums];
 };
+
+// Workgroup barrier.  L (LDS only): orders the LDS accesses of the
+// workgroup without waiting for the waves' outstanding global stores, for
+// barriers that publish nothing through global memory inside the workgroup.
+template <bool L = false>
+__device__ __forceinline__ void wg_barrier() {
+  if constexpr (L) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  } else {
+    __syncthreads();
+  }
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -105,20 +119,20 @@ constexpr int block_reduce_k_scratch() { return (K + 1) * (NT / 64 + 1); }
 // adds the per-wave partials itself; larger blocks let wave 0 reduce them
 // (one partial per lane), so the registers used do not grow with the block.
 // scratch: block_reduce_k_scratch<NT, K>() doubles.
-template <int NT, int K>
+template <int NT, int K, bool L = false>
 __device__ __forceinline__ void block_reduce_k(double (&v)[K], double& mx, double* scratch) {
   constexpr int NW = NT / 64;
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
   mx = wave_max(mx);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
+  wg_barrier<L>();
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) scratch[k * NW + wid] = v[k];
     scratch[K * NW + wid] = mx;
   }
-  __syncthreads();
+  wg_barrier<L>();
   if constexpr (NW <= 8) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -142,17 +156,17 @@ __device__ __forceinline__ void block_reduce_k(double (&v)[K], double& mx, doubl
       const double m = wave_max(lane < NW ? scratch[K * NW + lane] : -INFINITY);
       if (lane == 0) out[K] = m;
     }
-    __syncthreads();
+    wg_barrier<L>();
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = out[k];
     mx = out[K];
   }
-  __syncthreads();
+  wg_barrier<L>();
 }
 
 // Exclusive block scan of one non-negative value per thread; returns the
 // thread's prefix and writes the block total to *total.
-template <int NT = kBlock>
+template <int NT = kBlock, bool L = false>
 __device__ __forceinline__ long long block_exscan(long long v, long long* scratch /* NT/64 */,
                                                   long long* total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -162,9 +176,9 @@ __device__ __forceinline__ long long block_exscan(long long v, long long* scratc
     const long long t = __shfl_up(incl, o, 64);
     if (lane >= o) incl += t;
   }
-  __syncthreads();
+  wg_barrier<L>();
   if (lane == 63) scratch[wid] = incl;
-  __syncthreads();
+  wg_barrier<L>();
   long long base = 0, tot = 0;
 #pragma unroll
   for (int i = 0; i < NT / 64; ++i) {
@@ -176,7 +190,7 @@ __device__ __forceinline__ long long block_exscan(long long v, long long* scratc
 }
 
 // Two exclusive scans (a, b) in one LDS round trip.
-template <int NT>
+template <int NT, bool L = false>
 __device__ __forceinline__ void block_exscan2(long long a, long long b, long long* scratch /* 2*NT/64 */,
                                               long long* pa, long long* pb, long long* ta,
                                               long long* tb) {
@@ -191,12 +205,12 @@ __device__ __forceinline__ void block_exscan2(long long a, long long b, long lon
       ib += t2;
     }
   }
-  __syncthreads();
+  wg_barrier<L>();
   if (lane == 63) {
     scratch[wid] = ia;
     scratch[NT / 64 + wid] = ib;
   }
-  __syncthreads();
+  wg_barrier<L>();
   long long ba = 0, bb = 0, sa = 0, sb = 0;
 #pragma unroll
   for (int i = 0; i < NT / 64; ++i) {

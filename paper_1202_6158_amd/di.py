@@ -44,7 +44,8 @@ class DiError(RuntimeError):
 class Tune(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("c", ctypes.c_float),
                 ("window_log2", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("threads", ctypes.c_int32), ("tables", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("tables", ctypes.c_int32),
+                ("persist", ctypes.c_int32)]
 
 
 class TuneTrial(ctypes.Structure):
@@ -232,9 +233,9 @@ TABLES = {"auto": 0, "lds": 1, "global": 2}
 
 
 def make_tune(schedule="mean", c=1.0, window_log2=0, check_every=0, threads=0,
-              tables="auto") -> Tune:
+              tables="auto", persist=False) -> Tune:
     return Tune(SCHEDULE.get(schedule, schedule), float(c), int(window_log2), int(check_every),
-                int(threads), TABLES.get(tables, tables))
+                int(threads), TABLES.get(tables, tables), int(persist))
 
 
 def make_opts(d=0.85, tol=1e-8, precision="fp32", normalize=True, max_rounds=0, tune=None,
@@ -510,7 +511,8 @@ def tune_dict(t: Tune) -> dict:
     return {"schedule": _SCHED_NAME.get(t.schedule, t.schedule), "c": float(t.c),
             "window_log2": int(t.window_log2), "check_every": int(t.check_every),
             "threads": int(t.threads),
-            "tables": {v: k for k, v in TABLES.items()}.get(int(t.tables), int(t.tables))}
+            "tables": {v: k for k, v in TABLES.items()}.get(int(t.tables), int(t.tables)),
+            "persist": bool(t.persist)}
 
 
 def autotune(graph: Graph, mode="solve", d=0.85, tol=1e-8, precision="fp32", seed_ptr=None,
@@ -526,12 +528,13 @@ def autotune(graph: Graph, mode="solve", d=0.85, tol=1e-8, precision="fp32", see
         seeds = np.ascontiguousarray(seeds, dtype=np.int32)
         B = len(seed_ptr) - 1
     best = Tune()
-    trials = (TuneTrial * 64)()
+    cap = 160  # more than the tuner runs on any graph
+    trials = (TuneTrial * cap)()
     nt = ctypes.c_int32()
     _check(_lib.di_autotune(graph.handle, m, ctypes.byref(o), B, _ptr(seed_ptr), _ptr(seeds),
-                            ctypes.byref(best), trials, 64, ctypes.byref(nt), _stream(stream)))
+                            ctypes.byref(best), trials, cap, ctypes.byref(nt), _stream(stream)))
     out = [dict(tune_dict(trials[k].tune), seconds=trials[k].seconds, status=trials[k].status)
-           for k in range(min(nt.value, 64))]
+           for k in range(min(nt.value, cap))]
     return best, out
 
 

@@ -30,8 +30,12 @@ def test_autotune_solve_picks_fastest_and_caches(di):
     assert {t["schedule"] for t in trials} == {"mean", "op2", "op"}
     fastest = min(ok, key=lambda t: t["seconds"])
     assert di.tune_dict(best) == {k: fastest[k] for k in ("schedule", "c", "window_log2",
-                                                          "check_every", "threads", "tables")}
+                                                          "check_every", "threads", "tables",
+                                                          "persist")}
     assert {t["threads"] for t in trials} == {0, 1024}
+    # a 40-window graph: the one-launch solve is a candidate at every
+    # schedule x threshold factor
+    assert sum(t["persist"] for t in trials) >= 21
     # a solve that passes no tune uses the cached knobs: same rounds as the
     # explicit winner, and the result within its bound of the exact limit
     xs = oracle.sparse_exact(g, D)[1]

@@ -21,13 +21,21 @@ def di():
     return _di
 
 
+def _tune(di, sched, c, win):
+    """Windows of the default size (0), the whole-graph window (-1), or the
+    one-launch solve ("persist") at the default window."""
+    if win == "persist":
+        return di.make_tune(sched, c, persist=True)
+    return di.make_tune(sched, c, window_log2=win)
+
+
 @pytest.mark.parametrize("gname,prec,tol,sched", [
     ("pagerank-10k", "fp64", 1e-10, "mean"),
     ("pagerank-10k", "fp32", 1e-8, "mean"),
     ("pagerank-10k", "fp64", 1e-10, "op"),
     ("rand", "fp64", 1e-10, "op2"),
 ])
-@pytest.mark.parametrize("win", [0, -1], ids=["windows", "whole"])
+@pytest.mark.parametrize("win", [0, -1, "persist"], ids=["windows", "whole", "persist"])
 def test_replay_of_recorded_sets(di, gname, prec, tol, sched, win):
     import torch
     g = wl.recipe(gname) if gname != "rand" else wl.random_small(5000, 40000, seed=41, p_dangling=0.2)
@@ -38,7 +46,7 @@ def test_replay_of_recorded_sets(di, gname, prec, tol, sched, win):
     F0 = F.cpu().numpy().astype(np.float64)
     trace = torch.zeros((400, g.n), dtype=torch.uint8, device="cuda")
     _, st = di.solve(G, d=D, tol=tol, precision=prec, state=(F, H), trace=trace,
-                     tune=di.make_tune(sched, 1.0, window_log2=win))
+                     tune=_tune(di, sched, 1.0, win))
     rounds = st["rounds"]
     assert 0 < rounds <= 400
     sets = trace[:rounds].cpu().numpy().astype(bool)
@@ -75,7 +83,7 @@ def _score(sched, F, outdeg, indeg):
     ("rand", "op", 1.0),
     ("rand", "op2", 0.5),
 ])
-@pytest.mark.parametrize("win", [0, -1], ids=["windows", "whole"])
+@pytest.mark.parametrize("win", [0, -1, "persist"], ids=["windows", "whole", "persist"])
 def test_every_round_takes_the_top_of_its_score(di, gname, sched, c, win):
     """Every round of a traced fp64 solve takes an upper set of the schedule's
     score: on the oracle's replay of the recorded sets, each round's lowest
@@ -92,7 +100,7 @@ def test_every_round_takes_the_top_of_its_score(di, gname, sched, c, win):
     F0 = F.cpu().numpy()
     trace = torch.zeros((600, g.n), dtype=torch.uint8, device="cuda")
     _, st = di.solve(G, d=D, tol=1e-10, precision="fp64", state=(F, H), trace=trace,
-                     tune=di.make_tune(sched, c, window_log2=win))
+                     tune=_tune(di, sched, c, win))
     rounds = st["rounds"]
     assert 0 < rounds <= 600
     sets = trace[:rounds].cpu().numpy().astype(bool)
