@@ -349,6 +349,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   __shared__ double s_bsh[kSuper];
   __shared__ double s_red[block_reduce_k_scratch<NT, kSums>()];
   __shared__ long long s_scr[2 * (kRT / 64)];
+  __shared__ int s_lp;
 
   const int64_t j0 = (int64_t)b << a.wlog;
   const int wn = (int)min((int64_t)W, a.n - j0);
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int f = 0; f < kSums; ++f) v[f] = mine ? p_own.sum[f] : 0.0;
     double mrem_prev = mine ? __longlong_as_double((long long)p_own.mrem) : 0.0;
-    block_reduce_k<kRT, kSums>(v, mrem_prev, s_red);
+    block_reduce_k<kRT, kSums, true>(v, mrem_prev, s_red);
     const double nf = v[0], snd = v[1], sd = v[2], ssc = v[3], nnz = v[4], taken = v[5],
                  edges = v[6];
     int reason = 0;
@@ -492,9 +493,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       }
     }
   }
-  __syncthreads();
+  wg_barrier<true>();
   long long total = 0;  // records addressed to this window in round r-1
-  if (r >= 1) total = lds_exscan<kRT>(s_pre, nb, s_scr);
+  if (r >= 1) total = lds_exscan<kRT, true>(s_pre, nb, s_scr);
   if (total == 0 && !was_active) return;  // nothing held, nothing arrived: nothing to send
   if (total > 0) {
     const PairT<T>* pr = a.pairs[(r - 1) & 1] + (int64_t)vb * a.mrec;
@@ -535,15 +536,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     // The counts are consumed: clear the row for the launch that next writes it.
     for (int s = tid; s < nb; s += kRT) cnt_in[s] = 0;
   }
-  __syncthreads();
+  wg_barrier<true>();
   if (stop) {
     for (int q = tid; q < wn; q += kRT) Fv[j0 + q] = (T)win[q];
     return;
   }
 
   // 3. Take and expand, one tile of kRT nodes at a time.
+  if (tid == 0) s_lp = 0;
   for (int w = tid; w < nb; w += kRT) s_pre[w] = 0;  // now: records written per destination
-  __syncthreads();
+  wg_barrier<true>();
   int32_t* const cnt_out = a.cnt[r & 1] + vb * nb2;  // destination-major, non-zero entries only
   PairT<T>* out = a.pairs[r & 1] + (int64_t)vb * a.mrec;
   const uint32_t wmask = (uint32_t)W - 1u;
@@ -604,12 +606,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       }
     }
   }
-  __syncthreads();
+  wg_barrier<true>();
   // When the list can hold them, list the taken nodes in node order (chunk
   // offsets plus the rank within the chunk) and run the passes over the list;
   // otherwise every pass walks kSuper consecutive nodes.
   // (a window of at most kSuper nodes is one pass either way: no list)
-  const long long ntk = W > kSuper ? lds_exscan<kRT>(s_chunk, W >> 6, s_scr) : 0;
+  const long long ntk = W > kSuper ? lds_exscan<kRT, true>(s_chunk, W >> 6, s_scr) : 0;
   const bool use_list = W > kSuper && ntk <= list_cap;
   if (use_list && ntk > 0) {
     for (int q = tid, k = 0; q < W; q += kRT, ++k) {
@@ -619,7 +621,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
       if (t) s_list[s_chunk[q >> 6] + rank] = (uint16_t)q;
     }
-    __syncthreads();
+    wg_barrier<true>();
   }
   const int tlim = use_list ? (int)ntk : wn;
   int local_push = 0;  // some push stayed inside the window (its fluid is in LDS)
@@ -671,7 +673,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     }
     // C. Stage the pushing nodes (thread-major order) with their link offsets.
     long long slot = 0, eoff = 0, ntile = 0, etile = 0;
-    block_exscan2<kRT>(npush, nedge, s_scr, &slot, &eoff, &ntile, &etile);
+    block_exscan2<kRT, true>(npush, nedge, s_scr, &slot, &eoff, &ntile, &etile);
     if (ntile == 0) continue;  // uniform
 #pragma unroll
     for (int u = 0; u < kNPT; ++u) {
@@ -683,7 +685,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       ++slot;
       eoff += dg;
     }
-    __syncthreads();
+    wg_barrier<true>();
     // D. Push every staged link: each thread takes kRun consecutive links,
     //    one search for the node of the first, then a forward walk.  A link
     //    into this window whose target is not an S node still to be expanded
@@ -751,7 +753,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       }
     }
     acc[6] += (double)etile;  // uniform: counted once below (thread 0 only)
-    __syncthreads();
+    wg_barrier<true>();
   }
   for (int w = tid; w < nb; w += kRT)
     if (s_pre[w] > 0) {
@@ -763,10 +765,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   for (int q = tid; q < wn; q += kRT) Fv[j0 + q] = (T)win[q];
 
   // 4. This window's sums, added into its slot.
-  const int local_any = __syncthreads_or(local_push);
+  if (local_push) s_lp = 1;
+  wg_barrier<true>();
+  const int local_any = s_lp;
   const double edges = acc[6];
   acc[6] = 0.0;
-  block_reduce_k<kRT, kSums>(acc, mrem, s_red);
+  block_reduce_k<kRT, kSums, true>(acc, mrem, s_red);
   if (tid == 0) {
     acc[6] = edges;
     // the window stays active while some node keeps fluid: untaken, or
