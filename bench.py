@@ -427,7 +427,10 @@ def bench_c1(di, args):
     G = di.Graph(g)
     tol = 1e-10
     tune = None
-    if not args.no_autotune:
+    if args.c1_tune:  # fixed knobs (profiling runs)
+        f = args.c1_tune.split(":")
+        tune = di.make_tune(f[0], float(f[1]), int(f[2]), persist=len(f) > 3 and f[3] == "persist")
+    elif not args.no_autotune:
         tune, _ = di.autotune(G, "solve", d=0.85, tol=tol, precision="fp64")
     for _ in range(3):  # warm-up
         di.solve(G, d=0.85, tol=tol, precision="fp64", tune=tune)
@@ -708,6 +711,8 @@ def main():
                     help="run only this part and print its JSON (profiling runs)")
     ap.add_argument("--tune", metavar="SCHED:C:WLOG:THREADS",
                     help="fixed knobs for the single solve instead of autotuning (profiling runs)")
+    ap.add_argument("--c1-tune", metavar="SCHED:C:WLOG[:persist]",
+                    help="fixed knobs for the 10^4-node solve instead of autotuning (profiling runs)")
     ap.add_argument("--batch-tune", metavar="SCHED:C:WLOG:THREADS",
                     help="fixed knobs for the batch instead of autotuning (profiling runs)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
