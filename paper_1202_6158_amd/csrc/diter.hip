@@ -1486,7 +1486,8 @@ constexpr int kResLinkCap = 24576;         // out-links of a window held in LDS,
 constexpr int kResSpec = 4;                // speculative record reads per thread per round
 
 // Grid barrier of co-resident workgroups: an arrival counter that grows by
-// the number of workgroups every round (target = rounds so far x workgroups).
+// the number of workgroups every round (target = rounds so far x workgroups,
+// both modulo 2^32).
 // A wait longer than `limit` ticks of the constant-rate wall clock, or an
 // abort seen while waiting, sets bit 4 of *err and returns false: every
 // workgroup then leaves its loop at this or its next barrier.
@@ -1498,7 +1499,8 @@ __device__ bool grid_barrier(unsigned* bar, unsigned target, int* err, long long
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const long long t0 = wall_clock64();
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    // (compared as a signed difference: correct across the counter's wrap)
+    while ((int)(__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
       if ((__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 4) ||
           wall_clock64() - t0 > limit) {
         __hip_atomic_fetch_or(err, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
