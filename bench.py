@@ -429,7 +429,9 @@ def bench_c1(di, args):
     tune = None
     if args.c1_tune:  # fixed knobs (profiling runs)
         f = args.c1_tune.split(":")
-        tune = di.make_tune(f[0], float(f[1]), int(f[2]), persist=len(f) > 3 and f[3] == "persist")
+        if len(f) not in (3, 4) or (len(f) == 4 and f[3] != "persist"):
+            raise SystemExit("--c1-tune takes SCHED:C:WLOG or SCHED:C:WLOG:persist")
+        tune = di.make_tune(f[0], float(f[1]), int(f[2]), persist=len(f) == 4)
     elif not args.no_autotune:
         tune, _ = di.autotune(G, "solve", d=0.85, tol=tol, precision="fp64")
     for _ in range(3):  # warm-up
