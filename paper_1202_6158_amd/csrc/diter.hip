@@ -1483,7 +1483,7 @@ constexpr int kResMaxWindows = DI_PERSIST_MAX_WINDOWS;
 constexpr int kResMaxWlog = 11;
 constexpr int kResPass = 2 * kResThreads;  // taken nodes expanded per pass
 constexpr int kResLinkCap = 24576;         // out-links of a window held in LDS, at most
-constexpr int kResSpec = 4;                // speculative record reads per thread per round
+constexpr int kResSpec = 8;                // speculative record reads per thread per round
 
 // Grid barrier of co-resident workgroups: an arrival counter that grows by
 // the number of workgroups every round (target = rounds so far x workgroups,
