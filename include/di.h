@@ -107,8 +107,11 @@ typedef struct di_tune {
                           window's fluid, history, degrees and (when they fit) out-links held
                           in its workgroup's LDS for the whole solve, rounds separated by a grid
                           barrier; graphs of at most DI_PERSIST_MAX_WINDOWS windows of at most
-                          2^11 nodes (DI_EINVAL otherwise).  Same rounds, thresholds and stop as
-                          the launch-per-round path.  0 = one launch per round. */
+                          2^11 nodes (DI_EINVAL otherwise; window_log2 = 0 picks the smallest
+                          window that allows it).  Same rounds, thresholds and stop as the
+                          launch-per-round path.  A barrier wait past 2 s (a device fault, not a
+                          slow round) ends every workgroup's loop and the call returns
+                          DI_EDEVICE.  0 = one launch per round. */
 } di_tune;
 #define DI_PERSIST_MAX_WINDOWS 128
 
