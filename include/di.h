@@ -187,6 +187,17 @@ di_status di_graph_info(const di_graph* g, int64_t* n, int64_t* nnz, int64_t* n_
  */
 di_status di_set_taken_list(int32_t enable);
 
+/*
+ * Diagnostic setting, process-wide, for tests of a failure path.  A workgroup
+ * of the one-launch solve (di_tune.persist) that waits longer than `seconds`
+ * at a grid barrier (default 2; a wait that long means a device fault, not a
+ * slow round) ends the solve: every workgroup leaves its loop and di_solve
+ * returns DI_EDEVICE.  0 makes nearly every solve end that way, with every
+ * workgroup exiting normally.  Later launches use the new value.  DI_EINVAL
+ * unless 0 <= seconds <= 60.  Host only.
+ */
+di_status di_set_persist_wait(double seconds);
+
 /* --------------------------------------------------------- single solves */
 
 /*

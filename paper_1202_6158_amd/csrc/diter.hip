@@ -1892,6 +1892,9 @@ __global__ __launch_bounds__(kResThreads) void k_resident(DiArgs<T> a, int link_
   if (tid == 0) a.active[b] = active;
 }
 
+// Diagnostic setting (di_set_persist_wait): the longest barrier wait, seconds.
+static std::atomic<double> g_persist_wait_s{2.0};
+
 // Whether a single solve at 2^wlog-node windows can run as one launch.
 static bool resident_fits(int64_t n, int64_t m, int wlog, bool gt) {
   const int64_t nb = (n + (1ll << wlog) - 1) >> wlog;
@@ -1931,9 +1934,10 @@ static void launch_resident(const DiArgs<T>& a, int sched, hipStream_t s, Launch
   }();
   const size_t base = res_lds_bytes(a.wlog, a.nb, 0);
   DI_REQUIRE(base <= dyn_limit, "window too large for the one-launch solve");
+  // a barrier wait this long means a fault, not a slow round (di_set_persist_wait)
   int link_cap = (int)std::min<size_t>((dyn_limit - base) / 4, (size_t)kResLinkCap);
   const size_t smem = res_lds_bytes(a.wlog, a.nb, link_cap);
-  long long limit = 2 * ticks_per_s;  // a barrier wait of 2 s means a fault, not a slow round
+  long long limit = (long long)((double)ticks_per_s * g_persist_wait_s.load(std::memory_order_relaxed));
   DiArgs<T> args = a;
   void* params[] = {(void*)&args, (void*)&link_cap, (void*)&limit};
   const void* kern = sched == DI_SCHED_OP2  ? (const void*)k_resident<T, DI_SCHED_OP2>
@@ -2759,6 +2763,13 @@ di_status di_solve_batch(const di_graph* gc, int32_t B, const int64_t* seed_ptr,
              : batch_impl<float>(g, B, seed_ptr, seeds, seed_w, opts, x, stats, s);
   });
   return g != DI_OK ? g : rc;
+}
+
+di_status di_set_persist_wait(double seconds) {
+  return guarded([&] {
+    DI_REQUIRE(seconds >= 0.0 && seconds <= 60.0, "seconds must be within [0, 60]");
+    g_persist_wait_s.store(seconds, std::memory_order_relaxed);
+  });
 }
 
 di_status di_set_taken_list(int32_t enable) {

@@ -115,6 +115,7 @@ _SIGS = {
     "di_graph_info": [_P, _P, _P, _P],
     "di_window_layout": [ctypes.c_int64, ctypes.POINTER(Tune), _P, _P],
     "di_set_taken_list": [ctypes.c_int32],
+    "di_set_persist_wait": [ctypes.c_double],
     "di_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_power_solve": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
     "di_power_solve_noalloc": [_P, _P, ctypes.POINTER(Opts), _P, ctypes.POINTER(Stats), _P],
@@ -159,6 +160,12 @@ def set_taken_list(enable: bool):
     """di_set_taken_list: diagnostic, process-wide; False forces the round
     kernel's fallback of passes over consecutive nodes."""
     _check(_lib.di_set_taken_list(1 if enable else 0))
+
+
+def set_persist_wait(seconds: float):
+    """di_set_persist_wait: diagnostic, process-wide; the longest grid-barrier
+    wait of the one-launch solve before it ends with DI_EDEVICE."""
+    _check(_lib.di_set_persist_wait(float(seconds)))
 
 
 def window_layout(n: int, tune=None):

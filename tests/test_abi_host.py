@@ -125,3 +125,11 @@ def test_taken_list_switch_is_host_only_and_checked():
     assert di._lib.di_set_taken_list(-1) == di.EINVAL
     di.set_taken_list(False)
     di.set_taken_list(True)
+
+
+def test_persist_wait_setting_is_host_only_and_checked():
+    from paper_1202_6158_amd import di
+    assert di._lib.di_set_persist_wait(-1.0) == di.EINVAL and "seconds" in di.last_error()
+    assert di._lib.di_set_persist_wait(61.0) == di.EINVAL
+    di.set_persist_wait(0.5)
+    di.set_persist_wait(2.0)

@@ -4,8 +4,8 @@ separated by a grid barrier.  Limit parity against the oracle for every
 schedule and both precisions at every window size it takes (ragged last
 windows included), personalised, unnormalised and weighted solves, resume
 (Theorem 1 on the returned state), max_rounds, closed forms and degenerate
-graphs, the same rounds as the launch-per-round path, and the size limit.
-The frontier replay and the score rule of every round are checked in
+graphs, the same rounds as the launch-per-round path, the size limit, and
+the barrier's time-out path (forced from the host).  The frontier replay and the score rule of every round are checked in
 test_gpu_trace.py."""
 import numpy as np
 import pytest
@@ -156,3 +156,22 @@ def test_hub_window_reads_links_from_global_memory(di):
     G = di.Graph(g)
     x, st = di.solve(G, d=D, tol=1e-14, precision="fp64", tune=di.make_tune("op2", 0.5, 8, persist=True))
     assert _l1(x.cpu().numpy(), oracle.sparse_exact(g, D)[1]) <= 1e-12
+
+
+def test_barrier_wait_limit_ends_the_solve_cleanly(di, c1):
+    """The failure path of the grid barrier, forced from the host: with a wait
+    limit of 0 a workgroup that finds the others not yet arrived ends the
+    solve, every workgroup leaves its loop (the call returns), and the status
+    is DI_EDEVICE; the next solve, at the default limit, is exact again."""
+    g, xs = c1
+    G = di.Graph(g)
+    tune = di.make_tune("mean", 1.0, persist=True)
+    di.set_persist_wait(0.0)
+    try:
+        with pytest.raises(di.DiError) as e:
+            di.solve(G, d=D, tol=1e-10, precision="fp64", tune=tune)
+        assert e.value.status == di.EDEVICE and "barrier" in e.value.message
+    finally:
+        di.set_persist_wait(2.0)
+    x, st = di.solve(G, d=D, tol=1e-14, precision="fp64", tune=tune)
+    assert _l1(x.cpu().numpy(), xs) <= 1e-12
