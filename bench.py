@@ -418,6 +418,15 @@ def _time_solves(fn, reps):
     return float(np.median(ts)), r
 
 
+def parse_c1_tune(text):
+    """SCHED:C:WLOG[:persist] -> (schedule, c, window_log2, persist)."""
+    f = text.split(":")
+    if len(f) not in (3, 4) or (len(f) == 4 and f[3] != "persist") or \
+            f[0] not in ("mean", "op", "op2"):
+        raise SystemExit("--c1-tune takes SCHED:C:WLOG or SCHED:C:WLOG:persist")
+    return f[0], float(f[1]), int(f[2]), len(f) == 4
+
+
 def bench_c1(di, args):
     """The small graph: N = 10^4, mean degree 8, 10% dangling, fp64 fluid,
     ||F||_1 < 1e-10, against the fp64 power iteration to the same stop.
@@ -428,10 +437,8 @@ def bench_c1(di, args):
     tol = 1e-10
     tune = None
     if args.c1_tune:  # fixed knobs (profiling runs)
-        f = args.c1_tune.split(":")
-        if len(f) not in (3, 4) or (len(f) == 4 and f[3] != "persist"):
-            raise SystemExit("--c1-tune takes SCHED:C:WLOG or SCHED:C:WLOG:persist")
-        tune = di.make_tune(f[0], float(f[1]), int(f[2]), persist=len(f) == 4)
+        sched, c, wlog, persist = parse_c1_tune(args.c1_tune)
+        tune = di.make_tune(sched, c, wlog, persist=persist)
     elif not args.no_autotune:
         tune, _ = di.autotune(G, "solve", d=0.85, tol=tol, precision="fp64")
     for _ in range(3):  # warm-up

@@ -152,3 +152,11 @@ def test_cpu_leg_times_the_oracle_and_returns_its_references(bench):
     # the sequential MAT-ITER (exact up to its own stop) on the larger graph
     seq = oracle.power(big, 0.9, 1e-13)["x"]
     assert np.abs(refs["big"] - seq).sum() < 2 * 0.9 * 1e-12 / 0.1 + 1e-12
+
+
+def test_c1_knob_string(bench):
+    assert bench.parse_c1_tune("op:0.03125:8:persist") == ("op", 0.03125, 8, True)
+    assert bench.parse_c1_tune("op2:0.0625:9") == ("op2", 0.0625, 9, False)
+    for bad in ["op:0.03125", "op:0.03125:8:persis", "max:1:8", "op:1:8:persist:x"]:
+        with pytest.raises(SystemExit):
+            bench.parse_c1_tune(bad)
